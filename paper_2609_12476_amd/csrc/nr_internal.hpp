@@ -1,0 +1,115 @@
+// Internal definitions shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace nr {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kBlock = 256;      // four waves per workgroup
+constexpr int kMaxRadix = 8;     // FFT passes
+constexpr int kMaxDeg = 18;      // highest Chebyshev degree of the per-cell kernel polynomials
+constexpr int kMaxHorner = 28;   // highest degree of the tau series before the log1p/expm1 form
+
+// Per valid instance of a kernel class.  Lane-major point order: the
+// instance's L samples are cut into V = 64 * parts contiguous runs of C
+// samples; run v holds samples v*C .. v*C+C-1, and sample (v, s) lives at
+// entry (v / 64) * (C * 64) + s * 64 + (v % 64) of the instance's point
+// stream and of its segment's lane-major strain copy.  Lane l of the wave
+// for part p therefore walks run p*64+l in sample order while every load
+// of the wave is one contiguous 64-entry row.
+struct InstDev {
+    double a;           // tau scale (3/(5 beta)) u_s^{5/8}
+    double c;           // series variable per sample, (8/3) beta / (u_s fs); identity: 1/fs
+    double df;          // frequency period of the upsampled grid (bin spacing)
+    double fc;          // heterodyne frequency: f_lo + floor(K/2) df
+    int64_t strain_off; // first entry of the segment's lane-major strain copy
+    int64_t bin_off;    // first output bin of the instance
+    int64_t pt_off;     // first entry of the instance in the class point-stream layout
+    int32_t L;          // samples
+    int32_t C;          // samples per lane run
+    int32_t K;          // output bins
+    int32_t m0;         // floor(K/2): bin k holds mode m = k - m0
+    int32_t inst;       // plan instance index
+    int32_t seg;        // segment index
+    int32_t ndeg;       // tau: 0 identity; > 0 Horner degree in the sample index; < 0 log1p/expm1
+    int32_t coef_off;   // first Horner coefficient of this instance
+};
+
+// One segment of a class: where its samples are and where its lane-major copy goes.
+struct SegDev {
+    int64_t src_off;    // first sample in the caller's strain
+    int64_t dst_off;    // first entry of the lane-major copy
+    int32_t L;
+    int32_t C;
+};
+
+struct FftPlanDev {
+    int32_t n;
+    int32_t nr;              // number of passes
+    int32_t radix[kMaxRadix];
+};
+
+// Arguments of the tau and spreading kernels for one chunk of one class.
+struct SpreadArgs {
+    const InstDev* inst;     // class instances
+    const double* coef;      // Horner coefficients
+    const void* taps;        // [w][deg+1] Chebyshev coefficients of the per-cell kernel pieces
+    const void* strain_lm;   // lane-major strain copy of the class (real or complex)
+    void* points;            // staged point stream (chunk-relative)
+    void* grid;              // [chunk instances][n] complex
+    int64_t first;           // first class instance of the chunk
+    int64_t count;           // instances in the chunk
+    int64_t pt_base;         // pt_off of the first instance of the chunk
+    int32_t n;               // grid size
+    int32_t w;               // kernel width
+    int32_t parts;           // waves per instance (1, 2 or 4)
+    int32_t flush_period;    // steps between collective flushes (power of two)
+    int32_t strain_complex;
+    int32_t pad_;
+};
+
+struct EpilogueArgs {
+    const InstDev* inst;
+    const void* grid;        // [chunk instances][n] complex
+    const void* dec;         // [n] real deconvolution factors indexed by mode mod n
+    const void* twiddle;     // [n] complex exp(-2 pi i t / n)
+    FftPlanDev fft;
+    int64_t first;
+    int64_t count;
+    // spectra mode
+    void* spectra;           // complex output or null
+    void* power;             // real output or null
+    // segment-sum mode
+    const int32_t* tmpl_list;      // class instances of each class template, ascending
+    const int64_t* tmpl_list_off;  // [n class templates + 1]
+    const int64_t* tmpl_stat_off;  // stat offset of each class template
+    const int32_t* tmpl_id;        // plan template id of each class template
+    const double* seg_weight;      // [n_segs] or null
+    void* stat;
+    int32_t* n_used;
+    int32_t tmpl_first;            // class templates handled by this launch
+    int32_t tmpl_count;
+};
+
+// Launch wrappers (defined in nr_kernels.hip).
+hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int32_t parts,
+                                    const void* strain, int strain_fp64, int strain_complex,
+                                    void* dst, int dst_fp64, hipStream_t st);
+hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st);
+hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st);
+hipError_t launch_epilogue_spectra(const EpilogueArgs& a, int fp64, int out_fp64,
+                                   hipStream_t st);
+hipError_t launch_epilogue_sum(const EpilogueArgs& a, int fp64, int out_fp64, hipStream_t st);
+hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,
+                               const int32_t* inst_K, int64_t n_inv, void* spectra,
+                               void* power, int out_fp64, const uint8_t* mask, uint8_t* valid,
+                               int64_t n_inst, hipStream_t st);
+hipError_t launch_finite_scan(const void* strain, int64_t n, int fp64, int32_t* flag,
+                              hipStream_t st);
+size_t spread_lds_bytes(int fp64, int n);
+size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode);
+
+}  // namespace nr

@@ -1,0 +1,805 @@
+// gfx950 kernels of the semicoherent NUFFT resampling path.
+//
+//   strain_lane_major : per segment, copy the samples into the lane-major
+//                       order the spreader walks (see InstDev).
+//   tau               : (staged method) per sample, the resampled time offset
+//                       dtau_j = tau(t_j) - tau(t_s) of Eq. (new_t) in FP64
+//                       and its reduction modulo one grid period and one
+//                       heterodyne cycle, written as a point stream.
+//   spread            : "exponential of semicircle" kernel spreading onto a
+//                       periodic grid held in LDS (one grid per wave), with
+//                       per-cell Chebyshev moments; the fused method computes
+//                       the point stream inline instead of loading it.
+//   epilogue_*        : mixed-radix Stockham FFT in LDS, deconvolution by the
+//                       kernel's Fourier transform, |X|^2, and either the
+//                       per-instance outputs or the per-template segment sum.
+//
+// Type-I NUFFT construction (Sec. III.B and App. A: interpolation with a
+// kernel onto a uniform grid followed by an FFT): with the band centre f_c
+// and grid period df, c_j = x_j exp(-2 pi i f_c dtau_j) is spread at grid
+// position n * frac(df dtau_j); the DFT of the grid at mode m, divided by the
+// kernel's Fourier transform at 2 pi m / n, approximates
+// sum_j c_j exp(-2 pi i m df dtau_j) = X(f_c + m df).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "nr_internal.hpp"
+
+namespace nr {
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+struct PointOf;
+template <>
+struct PointOf<float> {
+    using type = uint2;  // (grid position, heterodyne phase) as 32-bit fractions of a period
+};
+template <>
+struct PointOf<double> {
+    using type = double2;  // the same two fractions in FP64
+};
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------ tau --
+
+// dtau_j = tau(t_s + j/fs) - tau(t_s) of Eq. (new_t).  With
+// y = (8/3) beta j / (u_s fs), dtau = a (1 - (1 - y)^{5/8}); the series in y
+// is a polynomial in j whose coefficients the plan stores per instance
+// (Horner in FP64); instances whose series converges too slowly use
+// a * (-expm1((5/8) log1p(-y))).  Both forms avoid the cancellation of the
+// direct difference of two values of size 3/(5 beta).
+__device__ __forceinline__ double dtau_of(const InstDev& d, const double* __restrict__ coef,
+                                          int64_t j)
+{
+    const double jd = (double)j;
+    if (d.ndeg == 0) return jd * d.c;
+    if (d.ndeg > 0) {
+        const double* b = coef + d.coef_off;
+        double acc = b[d.ndeg - 1];
+        for (int k = d.ndeg - 2; k >= 0; --k) acc = fma(acc, jd, b[k]);
+        return acc * jd;
+    }
+    return d.a * (-expm1(0.625 * log1p(-d.c * jd)));
+}
+
+// frac(x) as a 32-bit fixed-point fraction of one period, rounded to nearest.
+__device__ __forceinline__ uint32_t frac_u32(double x)
+{
+    double f = x - floor(x);
+    double y = rint(f * 4294967296.0);
+    y = (y >= 4294967296.0) ? 0.0 : y;
+    return (uint32_t)y;
+}
+
+__device__ __forceinline__ double frac_f64(double x) { return x - floor(x); }
+
+template <typename T>
+__device__ __forceinline__ typename PointOf<T>::type make_point(const InstDev& d,
+                                                                const double* __restrict__ coef,
+                                                                int64_t j);
+
+template <>
+__device__ __forceinline__ uint2 make_point<float>(const InstDev& d,
+                                                   const double* __restrict__ coef, int64_t j)
+{
+    const double dt = dtau_of(d, coef, j);
+    return make_uint2(frac_u32(d.df * dt), frac_u32(d.fc * dt));
+}
+
+template <>
+__device__ __forceinline__ double2 make_point<double>(const InstDev& d,
+                                                      const double* __restrict__ coef, int64_t j)
+{
+    const double dt = dtau_of(d, coef, j);
+    return make_double2(frac_f64(d.df * dt), frac_f64(d.fc * dt));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void tau_kernel(SpreadArgs a)
+{
+    using P = typename PointOf<T>::type;
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int parts = a.parts;
+    const int64_t item = (int64_t)blockIdx.x * (4 / parts) + wave / parts;
+    if (item >= a.count) return;
+    const int part = wave % parts;
+    const InstDev d = a.inst[a.first + item];
+    const int C = d.C;
+    const int64_t v = (int64_t)part * kWave + lane;
+    P* out = reinterpret_cast<P*>(a.points) + (d.pt_off - a.pt_base) + (int64_t)part * C * kWave + lane;
+    for (int s = 0; s < C; ++s) {
+        const int64_t j = v * C + s;
+        P pt;
+        if (j < d.L) {
+            pt = make_point<T>(d, a.coef, j);
+        } else {
+            pt.x = 0;
+            pt.y = 0;
+        }
+        out[(int64_t)s * kWave] = pt;
+    }
+}
+
+// --------------------------------------------------------------- spread --
+
+// sin and cos of 2 pi R / 2^32: exact octant reduction of the fixed-point
+// phase, then Taylor polynomials on [0, pi/4] (truncation < 3e-8).
+__device__ __forceinline__ void sincos_turn_u32(uint32_t R, float& s, float& c)
+{
+    const uint32_t o = R >> 29;
+    uint32_t rem = R & 0x1FFFFFFFu;
+    if (o & 1u) rem = 0x20000000u - rem;
+    const float th = (float)rem * 1.4629180792671596e-09f;  // 2 pi / 2^32
+    const float t2 = th * th;
+    float sn = fmaf(t2, 2.7557319e-06f, -1.9841270e-04f);
+    sn = fmaf(t2, sn, 8.3333333e-03f);
+    sn = fmaf(t2, sn, -1.6666667e-01f);
+    sn = fmaf(t2 * th, sn, th);
+    float cs = fmaf(t2, 2.4801587e-05f, -1.3888889e-03f);
+    cs = fmaf(t2, cs, 4.1666667e-02f);
+    cs = fmaf(t2, cs, -0.5f);
+    cs = fmaf(t2, cs, 1.0f);
+    const bool swap = ((o + 1u) >> 1) & 1u;
+    float cc = swap ? sn : cs;
+    float ss = swap ? cs : sn;
+    c = (((o + 2u) >> 2) & 1u) ? -cc : cc;
+    s = ((o >> 2) & 1u) ? -ss : ss;
+}
+
+// Decoded point: first grid cell g of its support (in [1, n]), the
+// Chebyshev variable u = 2 (g - (x - w/2)) - 1 in (-1, 1], and the
+// heterodyned strength (cr, ci) = x_j exp(-2 pi i r_j).
+template <typename T>
+struct Decoded {
+    int g;
+    T u, cr, ci;
+};
+
+template <typename T>
+__device__ __forceinline__ Decoded<T> decode(typename PointOf<T>::type p, T xr, T xi, int n,
+                                             int w);
+
+template <>
+__device__ __forceinline__ Decoded<float> decode<float>(uint2 p, float xr, float xi, int n, int w)
+{
+    Decoded<float> o;
+    const uint64_t X = (uint64_t)p.x * (uint32_t)n;         // position in 2^-32 cells
+    const uint64_t hq = (uint64_t)(uint32_t)w << 31;        // w/2 cells
+    uint64_t S = X - hq;
+    if (X < hq) S += (uint64_t)(uint32_t)n << 32;
+    o.g = (int)(S >> 32) + 1;
+    o.u = 1.0f - (float)(uint32_t)S * 4.656612873077393e-10f;  // 2^-31
+    float sn, cs;
+    sincos_turn_u32(p.y, sn, cs);
+    o.cr = xr * cs + xi * sn;
+    o.ci = xi * cs - xr * sn;
+    return o;
+}
+
+template <>
+__device__ __forceinline__ Decoded<double> decode<double>(double2 p, double xr, double xi, int n,
+                                                          int w)
+{
+    Decoded<double> o;
+    double S = p.x * (double)n - 0.5 * (double)w;
+    if (S < 0.0) S += (double)n;
+    const double fl = floor(S);
+    o.g = min(max((int)fl + 1, 1), n);
+    o.u = 2.0 * ((fl + 1.0) - S) - 1.0;
+    double sn, cs;
+    sincospi(2.0 * p.y, &sn, &cs);
+    o.cr = xr * cs + xi * sn;
+    o.ci = xi * cs - xr * sn;
+    return o;
+}
+
+template <typename T, int D>
+struct Moments {
+    T re[D + 1];
+    T im[D + 1];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int p = 0; p <= D; ++p) re[p] = im[p] = T(0);
+    }
+    // Add c * T_p(u) for p = 0..D (Chebyshev recurrence).
+    __device__ __forceinline__ void add(T u, T cr, T ci)
+    {
+        re[0] += cr;
+        im[0] += ci;
+        if (D >= 1) {
+            re[1] = fma(cr, u, re[1]);
+            im[1] = fma(ci, u, im[1]);
+        }
+        T t0 = T(1), t1 = u;
+        const T u2 = u + u;
+#pragma unroll
+        for (int p = 2; p <= D; ++p) {
+            const T t2 = fma(u2, t1, -t0);
+            re[p] = fma(cr, t2, re[p]);
+            im[p] = fma(ci, t2, im[p]);
+            t0 = t1;
+            t1 = t2;
+        }
+    }
+};
+
+__device__ __forceinline__ void lds_add(float* p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(double* p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Turn the moments of every point whose support starts at cell g into the
+// w tap sums and add them to the wave's LDS grid:
+//   tap t = sum_p A[t][p] M_p, added at cell (g + t) mod n.
+template <typename T, int D>
+__device__ __forceinline__ void flush(const Moments<T, D>& M, int g, const T* __restrict__ A,
+                                      cpx<T>* grid, int n, int w)
+{
+    for (int t = 0; t < w; ++t) {
+        const T* At = A + t * (D + 1);
+        T vr = T(0), vi = T(0);
+#pragma unroll
+        for (int p = 0; p <= D; ++p) {
+            vr = fma(At[p], M.re[p], vr);
+            vi = fma(At[p], M.im[p], vi);
+        }
+        int cell = g + t;
+        if (cell >= n) cell -= n;
+        lds_add(&grid[cell].x, vr);
+        lds_add(&grid[cell].y, vi);
+    }
+}
+
+// One wave per (instance, part).  Each lane walks its run of samples in
+// order; because tau is monotone in t the support's first cell g only
+// moves forward (and wraps once per period), so a lane keeps the Chebyshev
+// moments of the points sharing one g and turns them into kernel taps only
+// when g changes.  A change parks the finished moments; parked moments are
+// flushed by the whole wave every flush_period steps (or at once if a lane
+// changes cell twice within a period).  Each wave owns its grid copy, so
+// the LDS additions of one grid come from one wave in program order and the
+// result does not depend on scheduling.
+template <typename T, int D, bool FUSED>
+__global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
+{
+    using P = typename PointOf<T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int parts = a.parts;
+    const int n = a.n, w = a.w;
+    cpx<T>* grid = lds + wave * n;
+    for (int c = lane; c < n; c += kWave) grid[c] = cpx<T>{T(0), T(0)};
+    __syncthreads();
+
+    const int per_block = 4 / parts;
+    const int64_t item = (int64_t)blockIdx.x * per_block + wave / parts;
+    const int part = wave % parts;
+    const T* __restrict__ A = reinterpret_cast<const T*>(a.taps);
+
+    if (item < a.count) {
+        const InstDev d = a.inst[a.first + item];
+        const int C = d.C;
+        const int L = d.L;
+        const int64_t v = (int64_t)part * kWave + lane;
+        const int64_t row0 = (int64_t)part * C * kWave + lane;
+        const P* __restrict__ pts =
+            FUSED ? nullptr
+                  : reinterpret_cast<const P*>(a.points) + (d.pt_off - a.pt_base) + row0;
+        const int64_t xs0 = d.strain_off + row0;
+        const int fmask = a.flush_period - 1;
+
+        Moments<T, D> M, Sv;
+        M.zero();
+        Sv.zero();
+        int g_cur = -1, g_pend = -1;
+        for (int s = 0; s < C; ++s) {
+            const int64_t j = v * C + s;
+            if (j < L) {
+                P pt;
+                if (FUSED)
+                    pt = make_point<T>(d, a.coef, j);
+                else
+                    pt = pts[(int64_t)s * kWave];
+                T xr, xi;
+                if (a.strain_complex) {
+                    const cpx<T> xv = reinterpret_cast<const cpx<T>*>(a.strain_lm)[xs0 + (int64_t)s * kWave];
+                    xr = xv.x;
+                    xi = xv.y;
+                } else {
+                    xr = reinterpret_cast<const T*>(a.strain_lm)[xs0 + (int64_t)s * kWave];
+                    xi = T(0);
+                }
+                const Decoded<T> q = decode<T>(pt, xr, xi, n, w);
+                if (q.g != g_cur) {
+                    if (g_cur >= 0) {
+                        if (g_pend >= 0) flush<T, D>(Sv, g_pend, A, grid, n, w);
+                        Sv = M;
+                        g_pend = g_cur;
+                    }
+                    M.zero();
+                    g_cur = q.g;
+                }
+                M.add(q.u, q.cr, q.ci);
+            }
+            if ((s & fmask) == fmask) {
+                if (g_pend >= 0) {
+                    flush<T, D>(Sv, g_pend, A, grid, n, w);
+                    g_pend = -1;
+                }
+            }
+        }
+        if (g_pend >= 0) flush<T, D>(Sv, g_pend, A, grid, n, w);
+        if (g_cur >= 0) flush<T, D>(M, g_cur, A, grid, n, w);
+    }
+    __syncthreads();
+
+    if (item < a.count) {
+        // Sum the part grids of the instance in part order and store.
+        const int first_wave = (wave / parts) * parts;
+        cpx<T>* out = reinterpret_cast<cpx<T>*>(a.grid) + item * n;
+        for (int c = part * kWave + lane; c < n; c += kWave * parts) {
+            T r = T(0), i = T(0);
+            for (int q = 0; q < parts; ++q) {
+                const cpx<T> gv = lds[(first_wave + q) * n + c];
+                r += gv.x;
+                i += gv.y;
+            }
+            out[c] = cpx<T>{r, i};
+        }
+    }
+}
+
+// ------------------------------------------------------------------ FFT --
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return cpx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b)
+{
+    return cpx<T>{a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b)
+{
+    return cpx<T>{a.x - b.x, a.y - b.y};
+}
+// -i z
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a)
+{
+    return cpx<T>{a.y, -a.x};
+}
+
+// In-register DFT of length R (forward sign): y_q = sum_r v_r exp(-2 pi i r q / R).
+template <typename T>
+__device__ __forceinline__ void dft_small(cpx<T>* v, int R)
+{
+    if (R == 2) {
+        const cpx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if (R == 3) {
+        const T s3 = T(0.86602540378443864676);
+        const cpx<T> t = cadd(v[1], v[2]);
+        const cpx<T> d = csub(v[1], v[2]);
+        const cpx<T> m = cpx<T>{v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+        const cpx<T> r = cpx<T>{s3 * d.y, -s3 * d.x};  // -i s3 d
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, r);
+        v[2] = csub(m, r);
+    } else if (R == 4) {
+        const cpx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        const cpx<T> c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, mul_mi(d));
+        v[3] = csub(b, mul_mi(d));
+    } else {  // R == 5
+        const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+        const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+        const cpx<T> t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+        const cpx<T> t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+        const cpx<T> a1 = cpx<T>{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+        const cpx<T> a2 = cpx<T>{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+        const cpx<T> b1 = cpx<T>{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y};
+        const cpx<T> b2 = cpx<T>{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y};
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, mul_mi(b1));
+        v[4] = csub(a1, mul_mi(b1));
+        v[2] = cadd(a2, mul_mi(b2));
+        v[3] = csub(a2, mul_mi(b2));
+    }
+}
+
+// Stockham autosort FFT of the team's n points (ping-pong between buf[0..n)
+// and buf[n..2n)).  Pass with radix R and span Ns (product of the earlier
+// radices): butterfly j (0 <= j < n/R) takes inputs j + r n/R, applies the
+// twiddles exp(-2 pi i r k / (Ns R)) with k = j mod Ns, and writes output q
+// to (j / Ns) Ns R + k + q Ns.  Every thread of the block runs every pass.
+// Returns the buffer holding the result.
+template <typename T>
+__device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* __restrict__ tw, const FftPlanDev& fp,
+                            int tid, int ts)
+{
+    const int n = fp.n;
+    cpx<T>* src = buf;
+    cpx<T>* dst = buf + n;
+    int Ns = 1;
+    for (int p = 0; p < fp.nr; ++p) {
+        const int R = fp.radix[p];
+        const int nb = n / R;
+        const int twstep = n / (Ns * R);
+        for (int j = tid; j < nb; j += ts) {
+            const int k = j % Ns;
+            cpx<T> v[5];
+            v[0] = src[j];
+            for (int r = 1; r < R; ++r) v[r] = cmul(src[j + r * nb], tw[r * k * twstep]);
+            dft_small(v, R);
+            const int base = (j / Ns) * Ns * R + k;
+            for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
+        }
+        __syncthreads();
+        cpx<T>* t = src;
+        src = dst;
+        dst = t;
+        Ns *= R;
+    }
+    return src;
+}
+
+template <typename T>
+__device__ __forceinline__ int team_size_for(int n)
+{
+    return n <= 512 ? kWave : kBlock;
+}
+
+template <typename T, typename O>
+__global__ __launch_bounds__(kBlock) void epilogue_spectra_kernel(EpilogueArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int n = a.fft.n;
+    const int ts = team_size_for<T>(n);
+    const int team = threadIdx.x / ts, tid = threadIdx.x % ts;
+    const int nteam = kBlock / ts;
+    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw) + (size_t)team * 2 * n;
+    const int64_t item = (int64_t)blockIdx.x * nteam + team;
+    const bool live = item < a.count;
+    const cpx<T>* gsrc = reinterpret_cast<const cpx<T>*>(a.grid) + item * n;
+    if (live)
+        for (int c = tid; c < n; c += ts) buf[c] = gsrc[c];
+    __syncthreads();
+    const cpx<T>* res = fft_team<T>(buf, reinterpret_cast<const cpx<T>*>(a.twiddle), a.fft, tid, ts);
+    if (!live) return;
+    const InstDev d = a.inst[a.first + item];
+    const T* __restrict__ dec = reinterpret_cast<const T*>(a.dec);
+    cpx<O>* sp = reinterpret_cast<cpx<O>*>(a.spectra);
+    O* pw = reinterpret_cast<O*>(a.power);
+    for (int k = tid; k < d.K; k += ts) {
+        int l = k - d.m0;
+        if (l < 0) l += n;
+        const T f = dec[l];
+        const cpx<T> X = cpx<T>{res[l].x * f, res[l].y * f};
+        if (sp) sp[d.bin_off + k] = cpx<O>{(O)X.x, (O)X.y};
+        if (pw) pw[d.bin_off + k] = (O)X.x * (O)X.x + (O)X.y * (O)X.y;
+    }
+}
+
+// Segment sum: one workgroup per template; its instances inside the chunk
+// are shared round-robin by the teams, each team keeps FP64 partial sums,
+// and the partials are added in team order, so the result is reproducible.
+template <typename T, typename O>
+__global__ __launch_bounds__(kBlock) void epilogue_sum_kernel(EpilogueArgs a, int kmax)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int n = a.fft.n;
+    const int ts = team_size_for<T>(n);
+    const int team = threadIdx.x / ts, tid = threadIdx.x % ts;
+    const int nteam = kBlock / ts;
+    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw) + (size_t)team * 2 * n;
+    double* part = reinterpret_cast<double*>(reinterpret_cast<cpx<T>*>(smem_raw) + (size_t)nteam * 2 * n);
+    double* mine = part + (size_t)team * kmax;
+
+    const int ct = a.tmpl_first + blockIdx.x;
+    int64_t lo = a.tmpl_list_off[ct], hi = a.tmpl_list_off[ct + 1];
+    // entries of this chunk: class instances in [first, first + count)
+    {
+        int64_t l = lo, h = hi;
+        while (l < h) {
+            const int64_t m = (l + h) >> 1;
+            if (a.tmpl_list[m] < a.first) l = m + 1; else h = m;
+        }
+        const int64_t e0 = l;
+        h = hi;
+        while (l < h) {
+            const int64_t m = (l + h) >> 1;
+            if (a.tmpl_list[m] < a.first + a.count) l = m + 1; else h = m;
+        }
+        lo = e0;
+        hi = l;
+    }
+    const int64_t cnt = hi - lo;
+    if (cnt <= 0) return;  // uniform across the block
+    const InstDev d0 = a.inst[a.tmpl_list[lo]];
+    const int K = d0.K;
+    for (int k = tid; k < K; k += ts) mine[k] = 0.0;
+
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.twiddle);
+    const T* __restrict__ dec = reinterpret_cast<const T*>(a.dec);
+    const int64_t rounds = (cnt + nteam - 1) / nteam;
+    for (int64_t r = 0; r < rounds; ++r) {
+        const int64_t e = lo + r * nteam + team;
+        const bool live = e < hi;
+        int ci = 0;
+        if (live) {
+            ci = a.tmpl_list[e];
+            const cpx<T>* gsrc = reinterpret_cast<const cpx<T>*>(a.grid) + (int64_t)(ci - a.first) * n;
+            for (int c = tid; c < n; c += ts) buf[c] = gsrc[c];
+        }
+        __syncthreads();
+        const cpx<T>* res = fft_team<T>(buf, tw, a.fft, tid, ts);
+        if (live) {
+            const InstDev d = a.inst[ci];
+            const double wgt = a.seg_weight ? a.seg_weight[d.seg] : 1.0;
+            for (int k = tid; k < K; k += ts) {
+                int l = k - d.m0;
+                if (l < 0) l += n;
+                const T f = dec[l];
+                const T xr = res[l].x * f, xi = res[l].y * f;
+                mine[k] += wgt * ((double)xr * (double)xr + (double)xi * (double)xi);
+            }
+        }
+        __syncthreads();
+    }
+    O* stat = reinterpret_cast<O*>(a.stat) + a.tmpl_stat_off[ct];
+    for (int k = threadIdx.x; k < K; k += kBlock) {
+        double s = 0.0;
+        for (int t = 0; t < nteam; ++t) s += part[(size_t)t * kmax + k];
+        stat[k] = (O)((double)stat[k] + s);
+    }
+    if (threadIdx.x == 0 && a.n_used) a.n_used[a.tmpl_id[ct]] += (int32_t)cnt;
+}
+
+// ------------------------------------------------------------ utilities --
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void strain_lane_major_kernel(const SegDev* __restrict__ segs,
+                                                                   int32_t parts,
+                                                                   const Ti* __restrict__ src,
+                                                                   To* __restrict__ dst, int cplx)
+{
+    const int item = blockIdx.x;
+    const SegDev sd = segs[item / parts];
+    const int part = item % parts;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t v = (int64_t)part * kWave + lane;
+    const int64_t row0 = sd.dst_off + (int64_t)part * sd.C * kWave + lane;
+    for (int s = wave; s < sd.C; s += 4) {
+        const int64_t j = v * sd.C + s;
+        const int64_t o = row0 + (int64_t)s * kWave;
+        if (cplx) {
+            To re = To(0), im = To(0);
+            if (j < sd.L) {
+                re = (To)src[2 * (sd.src_off + j)];
+                im = (To)src[2 * (sd.src_off + j) + 1];
+            }
+            dst[2 * o] = re;
+            dst[2 * o + 1] = im;
+        } else {
+            dst[o] = (j < sd.L) ? (To)src[sd.src_off + j] : To(0);
+        }
+    }
+}
+
+template <typename O>
+__global__ void fill_invalid_kernel(const int32_t* __restrict__ inv, const int64_t* __restrict__ bin_off,
+                                    const int32_t* __restrict__ inst_K, int64_t n_inv, cpx<O>* sp,
+                                    O* pw, const uint8_t* __restrict__ mask, uint8_t* valid,
+                                    int64_t n_inst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (valid && i < n_inst) valid[i] = mask[i];
+    if (i < n_inv) {
+        const int32_t ii = inv[i];
+        const int64_t o = bin_off[ii];
+        for (int k = 0; k < inst_K[ii]; ++k) {
+            if (sp) sp[o + k] = cpx<O>{O(0), O(0)};
+            if (pw) pw[o + k] = O(0);
+        }
+    }
+}
+
+template <typename T>
+__global__ void finite_scan_kernel(const T* __restrict__ x, int64_t n, int32_t* flag)
+{
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(x[i]);
+    if (bad) atomicOr(flag, 1);
+}
+
+// ------------------------------------------------------------- launches --
+
+// Kernels whose dynamic LDS exceeds 64 KiB must opt in to the larger limit.
+template <typename K>
+static void allow_lds(K* kernel, size_t bytes)
+{
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t spread_lds_bytes(int fp64, int n)
+{
+    return (size_t)4 * n * (fp64 ? 16 : 8);
+}
+
+size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode)
+{
+    const int ts = n <= 512 ? kWave : kBlock;
+    const int nteam = kBlock / ts;
+    size_t b = (size_t)nteam * 2 * n * (fp64 ? 16 : 8);
+    if (sum_mode) b += (size_t)nteam * K_max * 8;
+    return b;
+}
+
+hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int32_t parts,
+                                    const void* strain, int strain_fp64, int strain_complex,
+                                    void* dst, int dst_fp64, hipStream_t st)
+{
+    if (n_segs <= 0) return hipSuccess;
+    dim3 grid((unsigned)(n_segs * parts)), block(kBlock);
+    if (strain_fp64 && dst_fp64)
+        strain_lane_major_kernel<double, double><<<grid, block, 0, st>>>(
+            segs, parts, (const double*)strain, (double*)dst, strain_complex);
+    else if (strain_fp64)
+        strain_lane_major_kernel<double, float><<<grid, block, 0, st>>>(
+            segs, parts, (const double*)strain, (float*)dst, strain_complex);
+    else if (dst_fp64)
+        strain_lane_major_kernel<float, double><<<grid, block, 0, st>>>(
+            segs, parts, (const float*)strain, (double*)dst, strain_complex);
+    else
+        strain_lane_major_kernel<float, float><<<grid, block, 0, st>>>(
+            segs, parts, (const float*)strain, (float*)dst, strain_complex);
+    return hipGetLastError();
+}
+
+hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st)
+{
+    if (a.count <= 0) return hipSuccess;
+    const int64_t per_block = 4 / a.parts;
+    dim3 grid((unsigned)((a.count + per_block - 1) / per_block)), block(kBlock);
+    if (fp64)
+        tau_kernel<double><<<grid, block, 0, st>>>(a);
+    else
+        tau_kernel<float><<<grid, block, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t launch_spread_d(const SpreadArgs& a, int fused, hipStream_t st)
+{
+    const int64_t per_block = 4 / a.parts;
+    dim3 grid((unsigned)((a.count + per_block - 1) / per_block)), block(kBlock);
+    const size_t lds = spread_lds_bytes(sizeof(T) == 8, a.n);
+    if (fused) {
+        allow_lds(spread_kernel<T, D, true>, lds);
+        spread_kernel<T, D, true><<<grid, block, lds, st>>>(a);
+    } else {
+        allow_lds(spread_kernel<T, D, false>, lds);
+        spread_kernel<T, D, false><<<grid, block, lds, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_spread_t(const SpreadArgs& a, int deg, int fused, hipStream_t st)
+{
+    switch (deg) {
+#define NR_CASE(DD) \
+    case DD: return launch_spread_d<T, DD>(a, fused, st);
+        NR_CASE(2) NR_CASE(3) NR_CASE(4) NR_CASE(5) NR_CASE(6) NR_CASE(7) NR_CASE(8) NR_CASE(9)
+        NR_CASE(10) NR_CASE(11) NR_CASE(12) NR_CASE(13) NR_CASE(14) NR_CASE(15) NR_CASE(16)
+        NR_CASE(17) NR_CASE(18)
+#undef NR_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st)
+{
+    if (a.count <= 0) return hipSuccess;
+    return fp64 ? launch_spread_t<double>(a, deg, fused, st)
+                : launch_spread_t<float>(a, deg, fused, st);
+}
+
+hipError_t launch_epilogue_spectra(const EpilogueArgs& a, int fp64, int out_fp64, hipStream_t st)
+{
+    if (a.count <= 0) return hipSuccess;
+    const int n = a.fft.n;
+    const int nteam = kBlock / (n <= 512 ? kWave : kBlock);
+    dim3 grid((unsigned)((a.count + nteam - 1) / nteam)), block(kBlock);
+    const size_t lds = epilogue_lds_bytes(fp64, n, 0, 0);
+    if (fp64) {
+        allow_lds(epilogue_spectra_kernel<double, double>, lds);
+        epilogue_spectra_kernel<double, double><<<grid, block, lds, st>>>(a);
+    } else if (out_fp64) {
+        allow_lds(epilogue_spectra_kernel<float, double>, lds);
+        epilogue_spectra_kernel<float, double><<<grid, block, lds, st>>>(a);
+    } else {
+        allow_lds(epilogue_spectra_kernel<float, float>, lds);
+        epilogue_spectra_kernel<float, float><<<grid, block, lds, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue_sum(const EpilogueArgs& a, int fp64, int out_fp64, hipStream_t st)
+{
+    if (a.count <= 0 || a.tmpl_count <= 0) return hipSuccess;
+    dim3 grid((unsigned)a.tmpl_count), block(kBlock);
+    const int kmax = a.fft.n;  // K <= n for every instance of a class
+    const size_t lds = epilogue_lds_bytes(fp64, a.fft.n, kmax, 1);
+    if (fp64) {
+        allow_lds(epilogue_sum_kernel<double, double>, lds);
+        epilogue_sum_kernel<double, double><<<grid, block, lds, st>>>(a, kmax);
+    } else if (out_fp64) {
+        allow_lds(epilogue_sum_kernel<float, double>, lds);
+        epilogue_sum_kernel<float, double><<<grid, block, lds, st>>>(a, kmax);
+    } else {
+        allow_lds(epilogue_sum_kernel<float, float>, lds);
+        epilogue_sum_kernel<float, float><<<grid, block, lds, st>>>(a, kmax);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,
+                               const int32_t* inst_K, int64_t n_inv, void* spectra, void* power,
+                               int out_fp64, const uint8_t* mask, uint8_t* valid, int64_t n_inst,
+                               hipStream_t st)
+{
+    const int64_t nthreads = n_inv > (valid ? n_inst : 0) ? n_inv : (valid ? n_inst : 0);
+    if (nthreads <= 0) return hipSuccess;
+    dim3 grid((unsigned)((nthreads + 255) / 256)), block(256);
+    if (out_fp64)
+        fill_invalid_kernel<double><<<grid, block, 0, st>>>(inv_inst, bin_off, inst_K, n_inv,
+                                                            (cpx<double>*)spectra, (double*)power,
+                                                            mask, valid, n_inst);
+    else
+        fill_invalid_kernel<float><<<grid, block, 0, st>>>(inv_inst, bin_off, inst_K, n_inv,
+                                                           (cpx<float>*)spectra, (float*)power,
+                                                           mask, valid, n_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite_scan(const void* strain, int64_t n, int fp64, int32_t* flag,
+                              hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (fp64)
+        finite_scan_kernel<double><<<(unsigned)blocks, 256, 0, st>>>((const double*)strain, n, flag);
+    else
+        finite_scan_kernel<float><<<(unsigned)blocks, 256, 0, st>>>((const float*)strain, n, flag);
+    return hipGetLastError();
+}
+
+}  // namespace nr

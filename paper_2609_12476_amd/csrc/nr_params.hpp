@@ -1,0 +1,46 @@
+// Host-side NUFFT and resampling parameters (no device code).
+#pragma once
+
+#include <vector>
+
+namespace nr {
+
+constexpr double kFp32MinTol = 1e-6;   // FP32 spreading/FFT reach about 1e-6 relative l2
+constexpr double kFp64MinTol = 1e-12;  // below this the kernel width table ends
+// Largest upsampled grid: four per-wave grid copies of the spreader share one
+// workgroup's LDS (160 KiB on gfx950).
+constexpr int kMaxGridF32 = 5120;
+constexpr int kMaxGridF64 = 2560;
+
+// beta(f0, Mc) of Eq. (beta) in s^-1 (0 for Mc = 0).
+double chirp_beta(double mc_msun, double f0);
+
+// Smallest ES kernel width whose calibrated relative error is <= tol / 2.
+int kernel_width(double tol, double sigma);
+
+// ES shape parameter for width w at upsampling sigma.
+double es_beta(int w, double sigma);
+
+// Upper bound on the relative l2 error of width w at upsampling sigma.
+double kernel_error(int w, double sigma);
+
+// Chebyshev coefficients of the w kernel pieces psi((t + fr - w/2)/(w/2)),
+// fr in [0, 1], t = 0..w-1, in the variable u = 2 fr - 1, truncated at the
+// smallest degree whose sup error is <= tol / 20 (at most max_deg).
+// Returns the degree; out holds w * (degree + 1) coefficients, tap-major.
+int kernel_pieces(int w, double beta, double tol, int max_deg, std::vector<long double>& out);
+
+// Fourier transform of the ES kernel of width w (grid units):
+//   psi_hat(xi) = int_{-w/2}^{w/2} exp(beta (sqrt(1 - (2x/w)^2) - 1)) cos(xi x) dx.
+long double es_fourier(int w, double beta, long double xi);
+
+// ES kernel value at z in [-1, 1].
+long double es_value(double beta, long double z);
+
+// Smallest 2^a 3^b 5^c >= m.
+int fft_size(long long m);
+
+// Radix passes of a 2^a 3^b 5^c size: fours, then a two, threes, fives.
+std::vector<int> fft_radices(int n);
+
+}  // namespace nr

@@ -1,0 +1,811 @@
+// Host plan runtime of the semicoherent NUFFT resampling library: argument
+// validation, per-instance resampling constants, kernel-class grouping,
+// NUFFT parameters, workspace and launch sequencing.  See
+// include/nufft_resample.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/nufft_resample.h"
+#include "nr_internal.hpp"
+#include "nr_params.hpp"
+
+using namespace nr;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct NrError : std::runtime_error {
+    nr_status code;
+    NrError(nr_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(nr_status c, const std::string& m) { throw NrError(c, m); }
+
+void hip_check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) fail(NR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    void alloc(size_t b, const char* what)
+    {
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            fail(NR_ERR_OUT_OF_MEMORY, std::string("device allocation of ") + std::to_string(b) +
+                                           " bytes for " + what + " failed: " + hipGetErrorString(e));
+        }
+        bytes = b;
+    }
+    template <typename T>
+    void upload(const std::vector<T>& v, const char* what)
+    {
+        alloc(v.size() * sizeof(T), what);
+        if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), what);
+    }
+};
+
+struct Chunk {
+    int64_t first, count, pt_base;
+    int32_t tmpl_first, tmpl_count;
+};
+
+struct Class {
+    int fp64, w, n, deg, parts;
+    double beta_es;
+    std::vector<int> radix;
+    std::vector<InstDev> inst;         // class instances, ascending plan index
+    std::vector<double> coef;          // Horner coefficients
+    std::vector<SegDev> segs;          // lane-major strain layout
+    int64_t strain_entries = 0;        // lane-major entries (complex counts once)
+    int64_t n_points = 0;              // sum of L
+    std::vector<Chunk> chunks;
+    // segment-sum bookkeeping
+    std::vector<int32_t> tmpl_id, tmpl_list;
+    std::vector<int64_t> tmpl_list_off, tmpl_stat_off;
+    // device copies
+    DevBuf d_inst, d_coef, d_taps, d_dec, d_tw, d_segs, d_strain, d_tmpl_id, d_tmpl_list,
+        d_tmpl_list_off, d_tmpl_stat_off;
+};
+
+}  // namespace
+
+struct nr_plan_s {
+    std::string err;
+    nr_options opt{};
+    hipStream_t stream = nullptr;
+    int32_t n_segs = 0, n_tmpls = 0;
+    int64_t n_inst = 0;
+    std::vector<nr_segment> segs;
+    std::vector<nr_template> tmpls;
+    std::vector<int32_t> inst_seg, inst_tmpl, inst_K;
+    std::vector<uint8_t> valid;
+    std::vector<int64_t> bin_off, stat_off;
+    std::vector<std::unique_ptr<Class>> classes;
+    int out_fp64 = 0, strain_fp64 = 0, method = NR_METHOD_FUSED;
+    int64_t n_valid = 0, valid_points = 0;
+    DevBuf d_points, d_grid, d_mask, d_bin_off, d_inst_K, d_invalid, d_flag;
+    int64_t n_invalid = 0;
+    int64_t workspace = 0;
+    int n_chunks = 0;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- checks --
+
+bool finite(double x) { return std::isfinite(x); }
+
+void validate(const nr_segment* segs, int32_t n_segs, const nr_template* tmpls, int32_t n_tmpls,
+              const nr_instance* inst, int64_t n_inst, double tol, const nr_options& o)
+{
+    if (!segs || n_segs <= 0) fail(NR_ERR_INVALID_ARG, "n_segs must be >= 1 with a segment array");
+    if (!tmpls || n_tmpls <= 0) fail(NR_ERR_INVALID_ARG, "n_tmpls must be >= 1 with a template array");
+    if (!(tol > 0.0 && tol <= 0.1) || !finite(tol)) fail(NR_ERR_INVALID_ARG, "tol must be in (0, 0.1]");
+    if (o.precision < NR_FP32 || o.precision > NR_AUTO) fail(NR_ERR_INVALID_ARG, "unknown precision");
+    if (o.method < NR_METHOD_AUTO || o.method > NR_METHOD_FUSED) fail(NR_ERR_INVALID_ARG, "unknown method");
+    if (o.sigma > 0.0 && !(o.sigma >= 1.25 && o.sigma <= 4.0))
+        fail(NR_ERR_INVALID_ARG, "sigma must be in [1.25, 4]");
+    if (o.parts != 0 && o.parts != 1 && o.parts != 2 && o.parts != 4)
+        fail(NR_ERR_INVALID_ARG, "parts must be 0, 1, 2 or 4");
+    if (o.strain_length < 0 || o.max_workspace_bytes < 0) fail(NR_ERR_INVALID_ARG, "negative size option");
+    for (int32_t s = 0; s < n_segs; ++s) {
+        const nr_segment& g = segs[s];
+        if (g.n_samples < 1 || g.n_samples > (int64_t(1) << 30))
+            fail(NR_ERR_INVALID_ARG, "segment " + std::to_string(s) + ": n_samples out of range");
+        if (g.sample_offset < 0) fail(NR_ERR_INVALID_ARG, "segment " + std::to_string(s) + ": negative offset");
+        if (!(g.fs > 0.0) || !finite(g.fs)) fail(NR_ERR_INVALID_ARG, "segment " + std::to_string(s) + ": fs must be > 0");
+        if (!finite(g.t_start)) fail(NR_ERR_INVALID_ARG, "segment " + std::to_string(s) + ": t_start not finite");
+        if (o.strain_length > 0 && g.sample_offset + g.n_samples > o.strain_length)
+            fail(NR_ERR_INVALID_ARG, "segment " + std::to_string(s) + " runs past the strain");
+    }
+    for (int32_t m = 0; m < n_tmpls; ++m) {
+        const nr_template& t = tmpls[m];
+        const std::string id = "template " + std::to_string(m);
+        if (!(t.mc_msun >= 0.0) || !finite(t.mc_msun)) fail(NR_ERR_INVALID_ARG, id + ": mc_msun must be >= 0");
+        if (t.mc_msun > 0.0 && (!(t.f0 > 0.0) || !finite(t.f0))) fail(NR_ERR_INVALID_ARG, id + ": f0 must be > 0");
+        if (t.n_bins < 1 || t.n_bins > (1 << 20)) fail(NR_ERR_INVALID_ARG, id + ": n_bins out of range");
+        if (!finite(t.f_lo) || !finite(t.df) || !finite(t.f_max)) fail(NR_ERR_INVALID_ARG, id + ": non-finite frequency");
+    }
+    if (inst) {
+        if (n_inst <= 0) fail(NR_ERR_INVALID_ARG, "n_inst must be >= 1 with an instance list");
+        for (int64_t i = 0; i < n_inst; ++i) {
+            if (inst[i].segment < 0 || inst[i].segment >= n_segs || inst[i].template_id < 0 ||
+                inst[i].template_id >= n_tmpls)
+                fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": index out of range");
+            if (!finite(inst[i].tol) || inst[i].tol > 0.1)
+                fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": tol must be <= 0.1");
+        }
+    } else if ((int64_t)n_segs * n_tmpls > (int64_t(1) << 31) - 1) {
+        fail(NR_ERR_INVALID_ARG, "too many instances");
+    }
+}
+
+// ------------------------------------------------------------ resampling --
+
+struct InstHost {
+    bool valid;
+    double beta;
+    long double a, c;  // tau scale and series variable per sample
+    double y_max;
+};
+
+// Validity rule and tau constants of one instance (long double host math).
+InstHost instance_constants(const nr_segment& g, const nr_template& t)
+{
+    InstHost h{};
+    h.beta = chirp_beta(t.mc_msun, t.f0);
+    if (h.beta == 0.0) {
+        h.valid = true;
+        h.c = 1.0L / (long double)g.fs;
+        return h;
+    }
+    const long double b = h.beta;
+    const long double us = 1.0L - (8.0L / 3.0L) * b * (long double)g.t_start;
+    const long double t_last = (long double)g.t_start + (long double)(g.n_samples - 1) / (long double)g.fs;
+    const long double ul = 1.0L - (8.0L / 3.0L) * b * t_last;
+    h.valid = (ul > 0.0L) && (us > 0.0L);
+    if (h.valid && t.f_max > 0.0) {
+        const long double f = (long double)t.f0 * powl(ul, -3.0L / 8.0L);
+        if (f > (long double)t.f_max) h.valid = false;
+    }
+    if (!h.valid) return h;
+    h.a = (3.0L / (5.0L * b)) * powl(us, 5.0L / 8.0L);
+    h.c = (8.0L / 3.0L) * b / (us * (long double)g.fs);
+    h.y_max = (double)(h.c * (long double)(g.n_samples - 1));
+    return h;
+}
+
+// Horner coefficients b_k (k = 1..d) of dtau(j) = a sum_k e_k (c j)^k, the
+// binomial series of 1 - (1 - y)^{5/8}; returns d, or -1 when the series
+// needs more than kMaxHorner terms for the requested phase accuracy.
+int horner_series(const InstHost& h, double f_ref, double cyc_tol, std::vector<double>& out)
+{
+    const long double y = h.y_max;
+    if (y <= 0.0L) {
+        out.push_back((double)(h.a * 0.625L * h.c));
+        return 1;
+    }
+    if (y >= 0.9L) return -1;
+    std::vector<long double> e(kMaxHorner + 2);
+    e[1] = 0.625L;
+    for (int k = 2; k <= kMaxHorner + 1; ++k) e[k] = e[k - 1] * ((long double)(k - 1) - 0.625L) / (long double)k;
+    int d = -1;
+    for (int k = 1; k <= kMaxHorner; ++k) {
+        // terms are positive and fall at least geometrically with ratio y
+        const long double tail = h.a * e[k + 1] * powl(y, (long double)(k + 1)) / (1.0L - y);
+        if (tail * (long double)f_ref <= (long double)cyc_tol) {
+            d = k;
+            break;
+        }
+    }
+    if (d < 0) return -1;
+    long double ck = 1.0L;
+    for (int k = 1; k <= d; ++k) {
+        ck *= h.c;
+        out.push_back((double)(h.a * e[k] * ck));
+    }
+    return d;
+}
+
+int default_parts(int64_t L)
+{
+    if (L <= 16384) return 1;
+    if (L <= 32768) return 2;
+    return 4;
+}
+
+struct ClassKey {
+    int fp64, w, n, parts;
+    bool operator<(const ClassKey& o) const
+    {
+        return std::tie(fp64, w, n, parts) < std::tie(o.fp64, o.w, o.n, o.parts);
+    }
+};
+
+template <typename T>
+std::vector<T> cast_vec(const std::vector<long double>& v)
+{
+    std::vector<T> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+    return o;
+}
+
+void build_class_tables(Class& c, double tol_cls, double sigma)
+{
+    // Chebyshev pieces of the kernel and the degree that reaches the target
+    std::vector<long double> taps;
+    c.deg = kernel_pieces(c.w, c.beta_es, tol_cls, kMaxDeg, taps);
+    // deconvolution factors 1/psi_hat(2 pi l' / n), l' = min(l, n - l)
+    std::vector<long double> dec(c.n);
+    for (int l = 0; l < c.n; ++l) {
+        const int lp = std::min(l, c.n - l);
+        dec[l] = 1.0L / es_fourier(c.w, c.beta_es, 2.0L * 3.14159265358979323846264338327950288L * lp / c.n);
+    }
+    std::vector<long double> tw(2 * (size_t)c.n);
+    for (int t = 0; t < c.n; ++t) {
+        const long double ang = -2.0L * 3.14159265358979323846264338327950288L * t / c.n;
+        tw[2 * t] = cosl(ang);
+        tw[2 * t + 1] = sinl(ang);
+    }
+    c.radix = fft_radices(c.n);
+    if (c.fp64) {
+        c.d_taps.upload(cast_vec<double>(taps), "kernel pieces");
+        c.d_dec.upload(cast_vec<double>(dec), "deconvolution");
+        c.d_tw.upload(cast_vec<double>(tw), "twiddles");
+    } else {
+        c.d_taps.upload(cast_vec<float>(taps), "kernel pieces");
+        c.d_dec.upload(cast_vec<float>(dec), "deconvolution");
+        c.d_tw.upload(cast_vec<float>(tw), "twiddles");
+    }
+    (void)sigma;
+}
+
+void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_template* tmpls,
+                 int32_t n_tmpls, const nr_instance* inst, int64_t n_inst, double tol)
+{
+    const nr_options& o = P.opt;
+    validate(segs, n_segs, tmpls, n_tmpls, inst, n_inst, tol, o);
+    const double sigma = o.sigma > 0.0 ? o.sigma : 2.0;
+    P.stream = (hipStream_t)o.stream;
+    P.n_segs = n_segs;
+    P.n_tmpls = n_tmpls;
+    P.segs.assign(segs, segs + n_segs);
+    P.tmpls.assign(tmpls, tmpls + n_tmpls);
+    P.n_inst = inst ? n_inst : (int64_t)n_segs * n_tmpls;
+    P.out_fp64 = o.precision != NR_FP32;
+    P.strain_fp64 = P.out_fp64;
+    P.method = (o.method == NR_METHOD_STAGED) ? NR_METHOD_STAGED : NR_METHOD_FUSED;
+
+    const int64_t N = P.n_inst;
+    P.inst_seg.resize(N);
+    P.inst_tmpl.resize(N);
+    P.inst_K.resize(N);
+    P.valid.assign(N, 0);
+    P.bin_off.resize(N + 1);
+    std::vector<double> inst_tol(N, tol);
+    for (int64_t i = 0; i < N; ++i) {
+        if (inst) {
+            P.inst_seg[i] = inst[i].segment;
+            P.inst_tmpl[i] = inst[i].template_id;
+            if (inst[i].tol > 0.0) inst_tol[i] = inst[i].tol;
+        } else {
+            P.inst_seg[i] = (int32_t)(i % n_segs);
+            P.inst_tmpl[i] = (int32_t)(i / n_segs);
+        }
+        P.inst_K[i] = P.tmpls[P.inst_tmpl[i]].n_bins;
+    }
+    P.bin_off[0] = 0;
+    for (int64_t i = 0; i < N; ++i) P.bin_off[i + 1] = P.bin_off[i] + P.inst_K[i];
+    P.stat_off.resize(n_tmpls + 1);
+    P.stat_off[0] = 0;
+    for (int32_t m = 0; m < n_tmpls; ++m) P.stat_off[m + 1] = P.stat_off[m] + P.tmpls[m].n_bins;
+
+    // Precision class and tolerance checks
+    for (int64_t i = 0; i < N; ++i) {
+        const double t = inst_tol[i];
+        if (o.precision == NR_FP32 && t < kFp32MinTol && o.strict)
+            fail(NR_ERR_TOL_UNATTAINABLE, "instance " + std::to_string(i) + ": FP32 cannot reach tol " +
+                                              std::to_string(t) + " (minimum 1e-6); use NR_FP64 or NR_AUTO");
+        if (t < kFp64MinTol && o.strict)
+            fail(NR_ERR_TOL_UNATTAINABLE, "instance " + std::to_string(i) + ": tol below 1e-12");
+    }
+
+    std::map<ClassKey, size_t> class_of;
+    std::map<ClassKey, double> class_tol;
+    std::vector<std::vector<int64_t>> members;
+    std::vector<std::vector<double>> coefs;
+    for (int64_t i = 0; i < N; ++i) {
+        const nr_segment& g = P.segs[P.inst_seg[i]];
+        const nr_template& t = P.tmpls[P.inst_tmpl[i]];
+        const InstHost h = instance_constants(g, t);
+        if (!h.valid) continue;
+        P.valid[i] = 1;
+        ++P.n_valid;
+        P.valid_points += g.n_samples;
+        int fp64 = o.precision == NR_FP64 ? 1 : 0;
+        if (o.precision == NR_AUTO && inst_tol[i] < kFp32MinTol) fp64 = 1;
+        const double tol_eff = std::max(inst_tol[i], fp64 ? kFp64MinTol : kFp32MinTol);
+        const int w = kernel_width(tol_eff, sigma);
+        const int K = t.n_bins;
+        const int n = fft_size(std::max((int64_t)std::ceil(sigma * K - 1e-9), (int64_t)2 * w));
+        const int n_max = fp64 ? kMaxGridF64 : kMaxGridF32;
+        if (n > n_max)
+            fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": grid size " + std::to_string(n) +
+                                         " exceeds the supported maximum " + std::to_string(n_max) +
+                                         " (lower n_bins or sigma)");
+        const int parts = o.parts ? o.parts : default_parts(g.n_samples);
+        ClassKey key{fp64, w, n, parts};
+        auto it = class_of.find(key);
+        size_t ci;
+        if (it == class_of.end()) {
+            ci = P.classes.size();
+            class_of[key] = ci;
+            class_tol[key] = tol_eff;
+            auto c = std::make_unique<Class>();
+            c->fp64 = fp64;
+            c->w = w;
+            c->n = n;
+            c->parts = parts;
+            c->beta_es = es_beta(w, sigma);
+            P.classes.push_back(std::move(c));
+            members.emplace_back();
+        } else {
+            ci = it->second;
+            class_tol[key] = std::min(class_tol[key], tol_eff);
+        }
+        Class& c = *P.classes[ci];
+        InstDev d{};
+        const double df = t.df > 0.0 ? t.df : g.fs / (double)g.n_samples;
+        d.df = df;
+        d.m0 = K / 2;
+        d.fc = t.f_lo + (double)d.m0 * df;
+        d.L = (int32_t)g.n_samples;
+        d.C = (int32_t)((g.n_samples + (int64_t)kWave * parts - 1) / ((int64_t)kWave * parts));
+        d.K = K;
+        d.inst = (int32_t)i;
+        d.seg = P.inst_seg[i];
+        d.a = (double)h.a;
+        d.c = (double)h.c;
+        if (h.beta == 0.0) {
+            d.ndeg = 0;
+        } else {
+            const double f_ref = std::fabs(t.f_lo) + (double)K * df + df;
+            const double cyc_tol = fp64 ? 1e-14 : 1e-11;
+            d.coef_off = (int32_t)c.coef.size();
+            d.ndeg = horner_series(h, f_ref, cyc_tol, c.coef);
+            if (d.ndeg < 0) d.coef_off = 0;
+        }
+        c.inst.push_back(d);
+        c.n_points += g.n_samples;
+    }
+    for (auto& kv : class_of) build_class_tables(*P.classes[kv.second], class_tol[kv.first], sigma);
+
+    // Lane-major strain layout per class, point-stream offsets, templates
+    const size_t psize_f = 8, psize_d = 16;
+    int64_t grid_chunk_bytes = 0, point_chunk_bytes = 0;
+    const int64_t cap = o.max_workspace_bytes > 0 ? o.max_workspace_bytes : (int64_t(8) << 30);
+    int64_t fixed_bytes = 0;
+    for (auto& cp : P.classes) {
+        Class& c = *cp;
+        std::map<int32_t, int64_t> seg_at;
+        const int esize = (c.fp64 ? 8 : 4) * (o.strain_complex ? 2 : 1);
+        int64_t pt = 0;
+        std::map<int32_t, int32_t> tmpl_at;
+        std::vector<std::vector<int32_t>> lists;
+        for (size_t k = 0; k < c.inst.size(); ++k) {
+            InstDev& d = c.inst[k];
+            auto it = seg_at.find(d.seg);
+            if (it == seg_at.end()) {
+                SegDev sd{};
+                sd.src_off = P.segs[d.seg].sample_offset;
+                sd.dst_off = c.strain_entries;
+                sd.L = d.L;
+                sd.C = d.C;
+                c.segs.push_back(sd);
+                seg_at[d.seg] = sd.dst_off;
+                c.strain_entries += (int64_t)c.parts * d.C * kWave;
+                d.strain_off = sd.dst_off;
+            } else {
+                d.strain_off = it->second;
+            }
+            d.pt_off = pt;
+            pt += (int64_t)c.parts * d.C * kWave;
+            d.bin_off = P.bin_off[d.inst];
+            const int32_t pm = P.inst_tmpl[d.inst];
+            auto jt = tmpl_at.find(pm);
+            if (jt == tmpl_at.end()) {
+                tmpl_at[pm] = (int32_t)c.tmpl_id.size();
+                c.tmpl_id.push_back(pm);
+                c.tmpl_stat_off.push_back(P.stat_off[pm]);
+                lists.emplace_back();
+                lists.back().push_back((int32_t)k);
+            } else {
+                lists[jt->second].push_back((int32_t)k);
+            }
+        }
+        c.tmpl_list_off.push_back(0);
+        for (auto& l : lists) {
+            c.tmpl_list.insert(c.tmpl_list.end(), l.begin(), l.end());
+            c.tmpl_list_off.push_back((int64_t)c.tmpl_list.size());
+        }
+        // class template of each class instance, to bound each chunk's template range
+        std::vector<int32_t> ct_of(c.inst.size());
+        for (size_t t = 0; t < lists.size(); ++t)
+            for (int32_t k : lists[t]) ct_of[k] = (int32_t)t;
+        fixed_bytes += c.strain_entries * esize;
+        // chunks bounded by the workspace cap
+        const int64_t gsize = (int64_t)c.n * (c.fp64 ? 16 : 8);
+        const int64_t psz = P.method == NR_METHOD_STAGED ? (c.fp64 ? psize_d : psize_f) : 0;
+        const int64_t budget = std::max<int64_t>(cap / 2, 1);
+        int64_t k0 = 0;
+        while (k0 < (int64_t)c.inst.size()) {
+            int64_t k1 = k0, gb = 0, pb = 0;
+            int32_t tlo = INT32_MAX, thi = -1;
+            while (k1 < (int64_t)c.inst.size()) {
+                const int64_t pts = (int64_t)c.parts * c.inst[k1].C * kWave;
+                if (k1 > k0 && (gb + gsize + pb + pts * psz > budget || k1 - k0 >= (int64_t(1) << 28))) break;
+                gb += gsize;
+                pb += pts * psz;
+                tlo = std::min(tlo, ct_of[k1]);
+                thi = std::max(thi, ct_of[k1]);
+                ++k1;
+            }
+            Chunk ch{k0, k1 - k0, c.inst[k0].pt_off, tlo, thi - tlo + 1};
+            c.chunks.push_back(ch);
+            grid_chunk_bytes = std::max(grid_chunk_bytes, gb);
+            point_chunk_bytes = std::max(point_chunk_bytes, pb);
+            k0 = k1;
+        }
+        P.n_chunks += (int)c.chunks.size();
+        // device tables
+        c.d_inst.upload(c.inst, "instances");
+        c.d_coef.upload(c.coef.empty() ? std::vector<double>{0.0} : c.coef, "tau series");
+        c.d_segs.upload(c.segs, "segments");
+        c.d_strain.alloc((size_t)c.strain_entries * esize, "lane-major strain");
+        c.d_tmpl_id.upload(c.tmpl_id, "templates");
+        c.d_tmpl_list.upload(c.tmpl_list, "template lists");
+        c.d_tmpl_list_off.upload(c.tmpl_list_off, "template lists");
+        c.d_tmpl_stat_off.upload(c.tmpl_stat_off, "template offsets");
+        P.workspace += (int64_t)(c.d_inst.bytes + c.d_coef.bytes + c.d_segs.bytes + c.d_strain.bytes +
+                                 c.d_taps.bytes + c.d_dec.bytes + c.d_tw.bytes + c.d_tmpl_id.bytes +
+                                 c.d_tmpl_list.bytes + c.d_tmpl_list_off.bytes + c.d_tmpl_stat_off.bytes);
+    }
+    if (fixed_bytes + grid_chunk_bytes + point_chunk_bytes > cap)
+        fail(NR_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(fixed_bytes + grid_chunk_bytes + point_chunk_bytes) +
+                                       " bytes exceeds max_workspace_bytes " + std::to_string(cap));
+    P.d_grid.alloc((size_t)grid_chunk_bytes, "grid");
+    if (P.method == NR_METHOD_STAGED) P.d_points.alloc((size_t)point_chunk_bytes, "point stream");
+    P.d_mask.upload(P.valid, "mask");
+    std::vector<int32_t> invalid;
+    for (int64_t i = 0; i < N; ++i)
+        if (!P.valid[i]) invalid.push_back((int32_t)i);
+    P.n_invalid = (int64_t)invalid.size();
+    P.d_invalid.upload(invalid, "invalid list");
+    P.d_bin_off.upload(P.bin_off, "bin offsets");
+    P.d_inst_K.upload(P.inst_K, "bins");
+    P.d_flag.alloc(sizeof(int32_t), "flag");
+    P.workspace += (int64_t)(P.d_grid.bytes + P.d_points.bytes + P.d_mask.bytes + P.d_invalid.bytes +
+                             P.d_bin_off.bytes + P.d_inst_K.bytes + P.d_flag.bytes);
+}
+
+// ------------------------------------------------------------ execution --
+
+SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
+{
+    SpreadArgs a{};
+    a.inst = (const InstDev*)c.d_inst.p;
+    a.coef = (const double*)c.d_coef.p;
+    a.taps = c.d_taps.p;
+    a.strain_lm = c.d_strain.p;
+    a.points = P.d_points.p;
+    a.grid = P.d_grid.p;
+    a.first = ch.first;
+    a.count = ch.count;
+    a.pt_base = ch.pt_base;
+    a.n = c.n;
+    a.w = c.w;
+    a.parts = c.parts;
+    a.flush_period = 16;
+    a.strain_complex = P.opt.strain_complex;
+    return a;
+}
+
+EpilogueArgs epilogue_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
+{
+    EpilogueArgs e{};
+    e.inst = (const InstDev*)c.d_inst.p;
+    e.grid = P.d_grid.p;
+    e.dec = c.d_dec.p;
+    e.twiddle = c.d_tw.p;
+    e.fft.n = c.n;
+    e.fft.nr = (int32_t)c.radix.size();
+    for (size_t r = 0; r < c.radix.size(); ++r) e.fft.radix[r] = c.radix[r];
+    e.first = ch.first;
+    e.count = ch.count;
+    e.tmpl_list = (const int32_t*)c.d_tmpl_list.p;
+    e.tmpl_list_off = (const int64_t*)c.d_tmpl_list_off.p;
+    e.tmpl_stat_off = (const int64_t*)c.d_tmpl_stat_off.p;
+    e.tmpl_id = (const int32_t*)c.d_tmpl_id.p;
+    e.tmpl_first = ch.tmpl_first;
+    e.tmpl_count = ch.tmpl_count;
+    return e;
+}
+
+void check_finite(nr_plan_s& P, const void* strain)
+{
+    if (!P.opt.check_finite) return;
+    int64_t total = 0;
+    for (auto& g : P.segs) total = std::max(total, g.sample_offset + g.n_samples);
+    if (P.opt.strain_complex) total *= 2;
+    hip_check(hipMemsetAsync(P.d_flag.p, 0, sizeof(int32_t), P.stream), "flag reset");
+    hip_check(launch_finite_scan(strain, total, P.strain_fp64, (int32_t*)P.d_flag.p, P.stream), "finite scan");
+    int32_t flag = 0;
+    hip_check(hipMemcpyAsync(&flag, P.d_flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, P.stream), "flag read");
+    hip_check(hipStreamSynchronize(P.stream), "finite scan");
+    if (flag) fail(NR_ERR_NONFINITE_INPUT, "strain contains NaN or Inf");
+}
+
+void run_front(nr_plan_s& P, Class& c, const Chunk& ch)
+{
+    SpreadArgs a = spread_args(P, c, ch);
+    if (P.method == NR_METHOD_STAGED) hip_check(launch_tau(a, c.fp64, P.stream), "tau kernel");
+    hip_check(launch_spread(a, c.fp64, c.deg, P.method == NR_METHOD_FUSED, P.stream), "spread kernel");
+}
+
+void lane_major(nr_plan_s& P, Class& c, const void* strain)
+{
+    hip_check(launch_strain_lane_major((const SegDev*)c.d_segs.p, (int32_t)c.segs.size(), c.parts, strain,
+                                       P.strain_fp64, P.opt.strain_complex, c.d_strain.p, c.fp64, P.stream),
+              "strain layout");
+}
+
+void execute(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid)
+{
+    if (!strain) fail(NR_ERR_INVALID_ARG, "strain is NULL");
+    check_finite(P, strain);
+    for (auto& cp : P.classes) {
+        Class& c = *cp;
+        lane_major(P, c, strain);
+        for (const Chunk& ch : c.chunks) {
+            run_front(P, c, ch);
+            EpilogueArgs e = epilogue_args(P, c, ch);
+            e.spectra = spectra;
+            e.power = power;
+            if (spectra || power)
+                hip_check(launch_epilogue_spectra(e, c.fp64, P.out_fp64, P.stream), "epilogue");
+        }
+    }
+    if (spectra || power || valid)
+        hip_check(launch_fill_invalid((const int32_t*)P.d_invalid.p, (const int64_t*)P.d_bin_off.p,
+                                      (const int32_t*)P.d_inst_K.p, (spectra || power) ? P.n_invalid : 0,
+                                      spectra, power, P.out_fp64, (const uint8_t*)P.d_mask.p, valid,
+                                      P.n_inst, P.stream),
+                  "invalid fill");
+}
+
+void semicoherent(nr_plan_s& P, const void* strain, const double* w, void* stat, int32_t* n_used)
+{
+    if (!strain || !stat) fail(NR_ERR_INVALID_ARG, "strain and stat must not be NULL");
+    check_finite(P, strain);
+    for (auto& cp : P.classes) {
+        Class& c = *cp;
+        lane_major(P, c, strain);
+        for (const Chunk& ch : c.chunks) {
+            run_front(P, c, ch);
+            EpilogueArgs e = epilogue_args(P, c, ch);
+            e.seg_weight = w;
+            e.stat = stat;
+            e.n_used = n_used;
+            hip_check(launch_epilogue_sum(e, c.fp64, P.out_fp64, P.stream), "segment sum");
+        }
+    }
+}
+
+template <typename F>
+nr_status guarded(nr_plan_s* P, F&& f)
+{
+    try {
+        f();
+        if (P) P->err.clear();
+        return NR_OK;
+    } catch (const NrError& e) {
+        if (P) P->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (P) P->err = "host allocation failed";
+        return NR_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        if (P) P->err = e.what();
+        return NR_ERR_DEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void nufft_resample_default_options(nr_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = NR_FP32;
+    opt->method = NR_METHOD_AUTO;
+    opt->sigma = 2.0;
+}
+
+nr_status nufft_resample_plan(nr_plan* out, const nr_segment* segs, int32_t n_segs,
+                              const nr_template* tmpls, int32_t n_tmpls, const nr_instance* inst,
+                              int64_t n_inst, double tol, const nr_options* opt)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return NR_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    nr_plan_s* P = nullptr;
+    try {
+        P = new nr_plan_s();
+    } catch (...) {
+        g_create_error = "host allocation failed";
+        return NR_ERR_OUT_OF_MEMORY;
+    }
+    if (opt)
+        P->opt = *opt;
+    else
+        nufft_resample_default_options(&P->opt);
+    nr_status st = guarded(P, [&] { create_plan(*P, segs, n_segs, tmpls, n_tmpls, inst, n_inst, tol); });
+    if (st != NR_OK) {
+        g_create_error = P->err;
+        delete P;
+        return st;
+    }
+    *out = P;
+    return NR_OK;
+}
+
+nr_status nufft_resample_execute(nr_plan p, const void* strain, void* spectra, void* power,
+                                 uint8_t* valid)
+{
+    if (!p) return NR_ERR_INVALID_ARG;
+    return guarded(p, [&] { execute(*p, strain, spectra, power, valid); });
+}
+
+nr_status nufft_resample_semicoherent_sum(nr_plan p, const void* strain, const double* seg_weight,
+                                          void* stat, int32_t* n_used)
+{
+    if (!p) return NR_ERR_INVALID_ARG;
+    return guarded(p, [&] { semicoherent(*p, strain, seg_weight, stat, n_used); });
+}
+
+nr_status nufft_resample_query(nr_plan p, nr_plan_info* info)
+{
+    if (!p || !info) return NR_ERR_INVALID_ARG;
+    std::memset(info, 0, sizeof(*info));
+    info->n_inst = p->n_inst;
+    info->n_valid = p->n_valid;
+    info->total_bins = p->bin_off.back();
+    info->stat_bins = p->stat_off.back();
+    info->valid_points = p->valid_points;
+    info->workspace_bytes = p->workspace;
+    info->n_classes = (int32_t)p->classes.size();
+    info->out_fp64 = p->out_fp64;
+    info->method = p->method;
+    info->n_chunks = p->n_chunks;
+    return NR_OK;
+}
+
+nr_status nufft_resample_query_class(nr_plan p, int32_t ci, nr_class_info* info)
+{
+    if (!p || !info || ci < 0 || ci >= (int32_t)p->classes.size()) {
+        if (p) p->err = "class index out of range";
+        return NR_ERR_INVALID_ARG;
+    }
+    const Class& c = *p->classes[ci];
+    std::memset(info, 0, sizeof(*info));
+    info->fp64 = c.fp64;
+    info->w = c.w;
+    info->n = c.n;
+    info->degree = c.deg;
+    info->parts = c.parts;
+    info->n_radix = (int32_t)c.radix.size();
+    for (size_t r = 0; r < c.radix.size() && r < 8; ++r) info->radix[r] = c.radix[r];
+    info->beta_es = c.beta_es;
+    info->n_inst = (int64_t)c.inst.size();
+    info->n_points = c.n_points;
+    return NR_OK;
+}
+
+nr_status nufft_resample_bin_offsets(nr_plan p, int64_t* offsets)
+{
+    if (!p || !offsets) return NR_ERR_INVALID_ARG;
+    std::memcpy(offsets, p->bin_off.data(), p->bin_off.size() * sizeof(int64_t));
+    return NR_OK;
+}
+
+nr_status nufft_resample_stat_offsets(nr_plan p, int64_t* offsets)
+{
+    if (!p || !offsets) return NR_ERR_INVALID_ARG;
+    std::memcpy(offsets, p->stat_off.data(), p->stat_off.size() * sizeof(int64_t));
+    return NR_OK;
+}
+
+nr_status nufft_resample_valid_mask(nr_plan p, uint8_t* valid)
+{
+    if (!p || !valid) return NR_ERR_INVALID_ARG;
+    std::memcpy(valid, p->valid.data(), p->valid.size());
+    return NR_OK;
+}
+
+nr_status nufft_resample_kernel_params(double tol, double sigma, int32_t precision, int32_t n_bins,
+                                       nr_class_info* info)
+{
+    if (!info || !(tol > 0.0 && tol <= 0.1) || n_bins < 1 || precision < NR_FP32 || precision > NR_AUTO ||
+        (sigma > 0.0 && !(sigma >= 1.25 && sigma <= 4.0))) {
+        g_create_error = "invalid kernel parameter query";
+        return NR_ERR_INVALID_ARG;
+    }
+    if (sigma <= 0.0) sigma = 2.0;
+    std::memset(info, 0, sizeof(*info));
+    const int fp64 = precision == NR_FP64 || (precision == NR_AUTO && tol < kFp32MinTol);
+    const double tol_eff = std::max(tol, fp64 ? kFp64MinTol : kFp32MinTol);
+    info->fp64 = fp64;
+    info->w = kernel_width(tol_eff, sigma);
+    info->beta_es = es_beta(info->w, sigma);
+    info->n = fft_size(std::max((long long)std::ceil(sigma * n_bins - 1e-9), (long long)2 * info->w));
+    std::vector<long double> taps;
+    info->degree = kernel_pieces(info->w, info->beta_es, tol_eff, kMaxDeg, taps);
+    const std::vector<int> r = fft_radices(info->n);
+    info->n_radix = (int32_t)r.size();
+    for (size_t k = 0; k < r.size() && k < 8; ++k) info->radix[k] = r[k];
+    info->parts = 1;
+    return NR_OK;
+}
+
+double nufft_resample_kernel_ft(int32_t w, double beta_es, double xi)
+{
+    if (w < 2 || w > 16 || !(beta_es > 0.0)) return NAN;
+    return (double)es_fourier(w, beta_es, (long double)xi);
+}
+
+double nufft_resample_chirp_beta(double mc_msun, double f0)
+{
+    if (!(mc_msun >= 0.0) || !(f0 > 0.0)) return NAN;
+    return chirp_beta(mc_msun, f0);
+}
+
+const char* nufft_resample_last_error(nr_plan p)
+{
+    return p ? p->err.c_str() : g_create_error.c_str();
+}
+
+void nufft_resample_destroy(nr_plan p)
+{
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    delete p;
+}
+
+}  // extern "C"

@@ -1,0 +1,364 @@
+"""Thin ctypes binding of the C ABI in include/nufft_resample.h.
+
+Every function here only marshals arguments: the computation runs in the
+gfx950 library ``libnufft_resample.so``.  PyTorch supplies device memory and
+the current HIP stream.  There is no CPU fallback: if the library is missing
+the import of this module's functions fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnufft_resample.so")
+
+NR_OK, NR_ERR_INVALID_ARG, NR_ERR_TOL_UNATTAINABLE, NR_ERR_OUT_OF_MEMORY, NR_ERR_DEVICE, \
+    NR_ERR_NONFINITE_INPUT = range(6)
+NR_FP32, NR_FP64, NR_AUTO = 0, 1, 2
+NR_METHOD_AUTO, NR_METHOD_STAGED, NR_METHOD_FUSED = 0, 1, 2
+
+_PRECISION = {"fp32": NR_FP32, "fp64": NR_FP64, "auto": NR_AUTO}
+_METHOD = {"auto": NR_METHOD_AUTO, "staged": NR_METHOD_STAGED, "fused": NR_METHOD_FUSED}
+
+
+class NrSegment(ctypes.Structure):
+    _fields_ = [("sample_offset", c_int64), ("n_samples", c_int64), ("fs", c_double),
+                ("t_start", c_double)]
+
+
+class NrTemplate(ctypes.Structure):
+    _fields_ = [("mc_msun", c_double), ("f0", c_double), ("f_lo", c_double), ("df", c_double),
+                ("n_bins", c_int32), ("reserved", c_int32), ("f_max", c_double)]
+
+
+class NrInstance(ctypes.Structure):
+    _fields_ = [("segment", c_int32), ("template_id", c_int32), ("tol", c_double)]
+
+
+class NrOptions(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("method", c_int32), ("sigma", c_double),
+                ("strain_complex", c_int32), ("strict", c_int32), ("check_finite", c_int32),
+                ("parts", c_int32), ("strain_length", c_int64), ("max_workspace_bytes", c_int64),
+                ("stream", c_void_p), ("tune_cache", c_char_p)]
+
+
+class NrPlanInfo(ctypes.Structure):
+    _fields_ = [("n_inst", c_int64), ("n_valid", c_int64), ("total_bins", c_int64),
+                ("stat_bins", c_int64), ("valid_points", c_int64), ("workspace_bytes", c_int64),
+                ("n_classes", c_int32), ("out_fp64", c_int32), ("method", c_int32),
+                ("n_chunks", c_int32)]
+
+
+class NrClassInfo(ctypes.Structure):
+    _fields_ = [("fp64", c_int32), ("w", c_int32), ("n", c_int32), ("degree", c_int32),
+                ("parts", c_int32), ("n_radix", c_int32), ("radix", c_int32 * 8),
+                ("beta_es", c_double), ("n_inst", c_int64), ("n_points", c_int64)]
+
+
+# symbol -> (restype, argtypes)
+SIGNATURES = {
+    "nufft_resample_default_options": (None, [ctypes.POINTER(NrOptions)]),
+    "nufft_resample_plan": (c_int32, [ctypes.POINTER(c_void_p), ctypes.POINTER(NrSegment), c_int32,
+                                      ctypes.POINTER(NrTemplate), c_int32,
+                                      ctypes.POINTER(NrInstance), c_int64, c_double,
+                                      ctypes.POINTER(NrOptions)]),
+    "nufft_resample_execute": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nufft_resample_semicoherent_sum": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
+                                                  c_void_p]),
+    "nufft_resample_query": (c_int32, [c_void_p, ctypes.POINTER(NrPlanInfo)]),
+    "nufft_resample_query_class": (c_int32, [c_void_p, c_int32, ctypes.POINTER(NrClassInfo)]),
+    "nufft_resample_bin_offsets": (c_int32, [c_void_p, c_void_p]),
+    "nufft_resample_stat_offsets": (c_int32, [c_void_p, c_void_p]),
+    "nufft_resample_valid_mask": (c_int32, [c_void_p, c_void_p]),
+    "nufft_resample_kernel_params": (c_int32, [c_double, c_double, c_int32, c_int32,
+                                               ctypes.POINTER(NrClassInfo)]),
+    "nufft_resample_kernel_ft": (c_double, [c_int32, c_double, c_double]),
+    "nufft_resample_chirp_beta": (c_double, [c_double, c_double]),
+    "nufft_resample_last_error": (c_char_p, [c_void_p]),
+    "nufft_resample_destroy": (None, [c_void_p]),
+}
+
+_lib = None
+
+
+class NrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nufft_resample error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load the gfx950 library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2609_12476_amd.build` (there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(code, plan=None):
+    if code != NR_OK:
+        msg = load().nufft_resample_last_error(plan)
+        raise NrError(code, msg.decode() if msg else "")
+
+
+def nufft_resample_default_options():
+    o = NrOptions()
+    load().nufft_resample_default_options(ctypes.byref(o))
+    return o
+
+
+def nufft_resample_plan(segs, tmpls, inst, tol, opt):
+    """segs / tmpls / inst: ctypes arrays (inst may be None). Returns a plan handle."""
+    h = c_void_p()
+    n_inst = len(inst) if inst is not None else 0
+    code = load().nufft_resample_plan(ctypes.byref(h), segs, len(segs), tmpls, len(tmpls), inst,
+                                      n_inst, float(tol), ctypes.byref(opt))
+    _check(code, None)
+    return h
+
+
+def nufft_resample_execute(plan, strain_ptr, spectra_ptr, power_ptr, valid_ptr):
+    _check(load().nufft_resample_execute(plan, strain_ptr, spectra_ptr, power_ptr, valid_ptr), plan)
+
+
+def nufft_resample_semicoherent_sum(plan, strain_ptr, weight_ptr, stat_ptr, n_used_ptr):
+    _check(load().nufft_resample_semicoherent_sum(plan, strain_ptr, weight_ptr, stat_ptr,
+                                                  n_used_ptr), plan)
+
+
+def nufft_resample_query(plan):
+    info = NrPlanInfo()
+    _check(load().nufft_resample_query(plan, ctypes.byref(info)), plan)
+    return info
+
+
+def nufft_resample_query_class(plan, c):
+    info = NrClassInfo()
+    _check(load().nufft_resample_query_class(plan, c, ctypes.byref(info)), plan)
+    return info
+
+
+def nufft_resample_bin_offsets(plan, n_inst):
+    out = np.empty(n_inst + 1, np.int64)
+    _check(load().nufft_resample_bin_offsets(plan, out.ctypes.data), plan)
+    return out
+
+
+def nufft_resample_stat_offsets(plan, n_tmpls):
+    out = np.empty(n_tmpls + 1, np.int64)
+    _check(load().nufft_resample_stat_offsets(plan, out.ctypes.data), plan)
+    return out
+
+
+def nufft_resample_valid_mask(plan, n_inst):
+    out = np.empty(n_inst, np.uint8)
+    _check(load().nufft_resample_valid_mask(plan, out.ctypes.data), plan)
+    return out
+
+
+def nufft_resample_kernel_params(tol, sigma=2.0, precision="fp32", n_bins=30):
+    info = NrClassInfo()
+    code = load().nufft_resample_kernel_params(float(tol), float(sigma), _PRECISION[precision],
+                                               int(n_bins), ctypes.byref(info))
+    _check(code, None)
+    return info
+
+
+def nufft_resample_kernel_ft(w, beta_es, xi):
+    return load().nufft_resample_kernel_ft(int(w), float(beta_es), float(xi))
+
+
+def nufft_resample_chirp_beta(mc_msun, f0):
+    return load().nufft_resample_chirp_beta(float(mc_msun), float(f0))
+
+
+def nufft_resample_last_error(plan=None):
+    m = load().nufft_resample_last_error(plan)
+    return m.decode() if m else ""
+
+
+def nufft_resample_destroy(plan):
+    if plan:
+        load().nufft_resample_destroy(plan)
+
+
+# ----------------------------------------------------------------------------
+# Convenience wrapper
+# ----------------------------------------------------------------------------
+
+def make_segments(seg_offset, seg_len, seg_fs, seg_t):
+    n = len(seg_offset)
+    arr = (NrSegment * n)()
+    for i in range(n):
+        arr[i] = NrSegment(int(seg_offset[i]), int(seg_len[i]), float(seg_fs[i]), float(seg_t[i]))
+    return arr
+
+
+def make_templates(mc, f0, f_lo, df, n_bins, f_max):
+    n = len(mc)
+    arr = (NrTemplate * n)()
+    for i in range(n):
+        arr[i] = NrTemplate(float(mc[i]), float(f0[i]), float(f_lo[i]), float(df[i]),
+                            int(n_bins[i]), 0, float(f_max[i]))
+    return arr
+
+
+def make_instances(inst_seg, inst_tmpl, inst_tol=None):
+    n = len(inst_seg)
+    arr = (NrInstance * n)()
+    for i in range(n):
+        arr[i] = NrInstance(int(inst_seg[i]), int(inst_tmpl[i]),
+                            float(inst_tol[i]) if inst_tol is not None else 0.0)
+    return arr
+
+
+class Plan:
+    """A planned batch of (segment, template) instances on the current GPU.
+
+    Inputs and outputs are torch tensors on the GPU; the plan enqueues on
+    ``stream`` (default: torch's current stream at construction).
+    """
+
+    def __init__(self, segs, tmpls, inst=None, tol=1e-6, precision="fp32", method="auto",
+                 sigma=2.0, strict=False, parts=0, strain_complex=False, strain_length=0,
+                 max_workspace_bytes=0, check_finite=False, stream=None):
+        import torch
+        opt = nufft_resample_default_options()
+        opt.precision = _PRECISION[precision]
+        opt.method = _METHOD[method]
+        opt.sigma = float(sigma)
+        opt.strict = int(bool(strict))
+        opt.parts = int(parts)
+        opt.strain_complex = int(bool(strain_complex))
+        opt.strain_length = int(strain_length)
+        opt.max_workspace_bytes = int(max_workspace_bytes)
+        opt.check_finite = int(bool(check_finite))
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        opt.stream = c_void_p(stream.cuda_stream) if stream is not None else None
+        self.precision = precision
+        self.strain_complex = bool(strain_complex)
+        self._segs, self._tmpls, self._inst = segs, tmpls, inst
+        self.handle = nufft_resample_plan(segs, tmpls, inst, tol, opt)
+        self.info = nufft_resample_query(self.handle)
+        self.n_segs, self.n_tmpls = len(segs), len(tmpls)
+        self.n_inst = self.info.n_inst
+        self.out_dtype = torch.float64 if self.info.out_fp64 else torch.float32
+        self.strain_dtype = self.out_dtype
+        need = max(int(s.sample_offset + s.n_samples) for s in segs)
+        self.strain_numel = need * (2 if self.strain_complex else 1)
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        inst = None
+        if w.inst_seg is not None:
+            inst = make_instances(w.inst_seg, w.inst_tmpl, w.inst_tol)
+        kw.setdefault("tol", w.tol)
+        kw.setdefault("strain_complex", np.iscomplexobj(w.strain))
+        kw.setdefault("strain_length", len(w.strain))
+        return cls(make_segments(w.seg_offset, w.seg_len, w.seg_fs, w.seg_t),
+                   make_templates(w.mc, w.f0, w.f_lo, w.df, w.n_bins, w.f_max), inst, **kw)
+
+    # -- host-side descriptions ------------------------------------------------
+    def classes(self):
+        return [nufft_resample_query_class(self.handle, c) for c in range(self.info.n_classes)]
+
+    def bin_offsets(self):
+        return nufft_resample_bin_offsets(self.handle, self.n_inst)
+
+    def stat_offsets(self):
+        return nufft_resample_stat_offsets(self.handle, self.n_tmpls)
+
+    def valid_mask(self):
+        return nufft_resample_valid_mask(self.handle, self.n_inst)
+
+    # -- device work -------------------------------------------------------------
+    def strain_tensor(self, x, device="cuda"):
+        """Device tensor of the strain in the plan's input layout (real or interleaved)."""
+        import torch
+        x = np.asarray(x)
+        if self.strain_complex:
+            x = np.ascontiguousarray(x.astype(np.complex128)).view(np.float64)
+        t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+        return t.to(device=device, dtype=self.strain_dtype)
+
+    def _check_strain(self, strain):
+        import torch
+        if not (isinstance(strain, torch.Tensor) and strain.is_cuda and strain.is_contiguous()):
+            raise ValueError("strain must be a contiguous CUDA tensor")
+        if strain.dtype != self.strain_dtype:
+            raise ValueError(f"strain dtype must be {self.strain_dtype}")
+        if strain.numel() < self.strain_numel:
+            raise ValueError(f"strain has {strain.numel()} values; the segments need {self.strain_numel}")
+
+    def execute(self, strain, spectra=None, power=None, valid=None, want=("spectra", "power", "valid")):
+        """Enqueue the spectra of every instance; returns the output tensors."""
+        import torch
+        self._check_strain(strain)
+        dev = strain.device
+        nb = self.info.total_bins
+        if spectra is None and "spectra" in want:
+            spectra = torch.empty(2 * nb, dtype=self.out_dtype, device=dev)
+        if power is None and "power" in want:
+            power = torch.empty(nb, dtype=self.out_dtype, device=dev)
+        if valid is None and "valid" in want:
+            valid = torch.empty(self.n_inst, dtype=torch.uint8, device=dev)
+        nufft_resample_execute(self.handle, c_void_p(strain.data_ptr()),
+                               c_void_p(spectra.data_ptr()) if spectra is not None else None,
+                               c_void_p(power.data_ptr()) if power is not None else None,
+                               c_void_p(valid.data_ptr()) if valid is not None else None)
+        return spectra, power, valid
+
+    def semicoherent_sum(self, strain, seg_weight=None, stat=None, n_used=None):
+        """Enqueue stat += segment sums (and n_used += counts); returns (stat, n_used)."""
+        import torch
+        self._check_strain(strain)
+        dev = strain.device
+        if stat is None:
+            stat = torch.zeros(self.info.stat_bins, dtype=self.out_dtype, device=dev)
+        if n_used is None:
+            n_used = torch.zeros(self.n_tmpls, dtype=torch.int32, device=dev)
+        wptr = None
+        if seg_weight is not None:
+            if seg_weight.dtype != torch.float64 or not seg_weight.is_cuda:
+                raise ValueError("seg_weight must be a float64 CUDA tensor")
+            wptr = c_void_p(seg_weight.data_ptr())
+        nufft_resample_semicoherent_sum(self.handle, c_void_p(strain.data_ptr()), wptr,
+                                        c_void_p(stat.data_ptr()), c_void_p(n_used.data_ptr()))
+        return stat, n_used
+
+    def close(self):
+        if getattr(self, "handle", None):
+            nufft_resample_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def complex_view(spectra):
+    """Interleaved (re, im) output -> complex tensor view."""
+    import torch
+    return torch.view_as_complex(spectra.view(-1, 2))

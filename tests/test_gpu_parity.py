@@ -1,0 +1,231 @@
+"""Parity of the gfx950 path (through the C ABI) with the oracle.
+
+Bounds: relative l2 over an instance's bins <= 1e-9 in FP64 and <= 1e-5 in
+FP32; segment sums <= 1e-9 (FP64) and <= 1e-4 (FP32) relative l2 per
+template; validity flags and segment counts bit-exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_SPEC = 1e-5
+FP32_SUM = 1e-4
+FP64_SPEC = 1e-9
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_plan(w, dev, **kw):
+    import torch
+    from paper_2609_12476_amd import Plan, complex_view
+    with Plan.from_workload(w, **kw) as p:
+        x = p.strain_tensor(w.strain, dev)
+        sp, pw, valid = p.execute(x)
+        torch.cuda.synchronize()
+        X = complex_view(sp).cpu().numpy().astype(np.complex128)
+        return X, pw.cpu().numpy().astype(np.float64), valid.cpu().numpy(), p.bin_offsets(), p.classes()
+
+
+def run_sum(w, dev, seg_weight=None, **kw):
+    import torch
+    from paper_2609_12476_amd import Plan
+    with Plan.from_workload(w, **kw) as p:
+        x = p.strain_tensor(w.strain, dev)
+        sw = None if seg_weight is None else torch.tensor(seg_weight, dtype=torch.float64, device=dev)
+        stat, used = p.semicoherent_sum(x, sw)
+        torch.cuda.synchronize()
+        return stat.cpu().numpy().astype(np.float64), used.cpu().numpy(), p.stat_offsets()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a)
+
+
+def per_instance_errors(X, Xr, off, ok):
+    errs = []
+    for i in range(len(off) - 1):
+        a, b = X[off[i]:off[i + 1]], Xr[off[i]:off[i + 1]]
+        if ok[i]:
+            errs.append(rel(a, b))
+        else:
+            assert not np.any(a), f"invalid instance {i} not zero"
+    return np.array(errs)
+
+
+# ------------------------------------------------------------ single segment --
+
+@pytest.mark.parametrize("method", ["fused", "staged"])
+def test_single_segment_fp64(gpu, method):
+    say(f"single_segment fp64 {method}")
+    w = synth.single_segment()
+    Xr, off, ok = oracle.spectra(w)
+    X, P, valid, off_g, cls = run_plan(w, gpu, precision="fp64", method=method, tol=1e-9)
+    assert np.array_equal(off, off_g) and valid[0] == 1
+    assert cls[0].n == 1200 and cls[0].fp64 == 1
+    e = rel(X, Xr)
+    say(f"  rel l2 = {e:.3e} (w={cls[0].w}, degree={cls[0].degree})")
+    assert e <= FP64_SPEC
+    assert np.allclose(P, np.abs(X) ** 2, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("method", ["fused", "staged"])
+def test_single_segment_fp32(gpu, method):
+    say(f"single_segment fp32 {method}")
+    w = synth.single_segment()
+    Xr, off, ok = oracle.spectra(w)
+    X, P, valid, _, cls = run_plan(w, gpu, precision="fp32", method=method, tol=1e-6)
+    e = rel(X, Xr)
+    say(f"  rel l2 = {e:.3e}")
+    assert e <= FP32_SPEC
+    assert np.allclose(P, np.abs(X) ** 2, rtol=1e-6, atol=1e-6 * np.max(P))
+
+
+def test_analytic_chirp_collapse_on_gpu(gpu):
+    say("analytic chirp collapse")
+    L, fs, A = 7680, 256.0, 0.05
+    t = np.arange(L) / fs
+    w = synth.single_segment()
+    w.strain = synth.injection(t, 50.0, 1e-2, A, analytic=True)
+    X, P, valid, _, _ = run_plan(w, gpu, precision="fp64", tol=1e-10, strain_complex=True)
+    assert np.argmax(P) == 300
+    assert abs(P[300] / (L * A / 2) ** 2 - 1.0) < 1e-9
+
+
+# ------------------------------------------------------------ semicoherent ----
+
+@pytest.mark.parametrize("prec,method", [("fp32", "fused"), ("fp32", "staged"), ("fp64", "fused"),
+                                         ("fp64", "staged")])
+def test_semicoherent_small(gpu, prec, method):
+    say(f"semicoherent small {prec} {method}")
+    w = synth.semicoherent(hours=0.1, n_mc=4, n_sub=3, seed=3, snr=30.0)
+    Xr, off, ok = oracle.spectra(w)
+    tol = 1e-6 if prec == "fp32" else 1e-10
+    X, P, valid, off_g, _ = run_plan(w, gpu, precision=prec, method=method, tol=tol)
+    assert np.array_equal(valid, ok) and np.array_equal(off, off_g)
+    errs = per_instance_errors(X, Xr, off, ok)
+    say(f"  {len(errs)} valid of {w.n_inst}; max rel {errs.max():.3e} median {np.median(errs):.3e}")
+    assert errs.max() <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
+    Sr, soff, used_r = oracle.semicoherent(w)
+    S, used, soff_g = run_sum(w, gpu, precision=prec, method=method, tol=tol)
+    assert np.array_equal(used, used_r) and np.array_equal(soff, soff_g)
+    for m in range(w.n_tmpl):
+        a, b = S[soff[m]:soff[m + 1]], Sr[soff[m]:soff[m + 1]]
+        if used_r[m]:
+            assert rel(a, b) <= (FP32_SUM if prec == "fp32" else FP64_SPEC), m
+        else:
+            assert not np.any(a)
+
+
+def test_semicoherent_weights_and_accumulation(gpu):
+    say("semicoherent weights")
+    import torch
+    from paper_2609_12476_amd import Plan
+    w = synth.semicoherent(hours=0.05, n_mc=3, n_sub=2, seed=8)
+    wts = np.linspace(0.25, 2.0, w.n_seg)
+    Sr, soff, used_r = oracle.semicoherent(w, seg_weight=wts)
+    with Plan.from_workload(w, precision="fp64", tol=1e-10) as p:
+        x = p.strain_tensor(w.strain, gpu)
+        sw = torch.tensor(wts, dtype=torch.float64, device=gpu)
+        stat, used = p.semicoherent_sum(x, sw)
+        stat, used = p.semicoherent_sum(x, sw, stat, used)    # accumulates
+        torch.cuda.synchronize()
+        S = stat.cpu().numpy()
+        assert np.array_equal(used.cpu().numpy(), 2 * used_r)
+        assert rel(S, 2 * Sr) <= FP64_SPEC
+
+
+def test_semicoherent_determinism(gpu):
+    say("determinism")
+    w = synth.semicoherent(hours=0.1, n_mc=4, n_sub=3, seed=5)
+    a = run_sum(w, gpu, precision="fp32", tol=1e-6)[0]
+    b = run_sum(w, gpu, precision="fp32", tol=1e-6)[0]
+    assert np.array_equal(a, b)
+    X1 = run_plan(w, gpu, precision="fp32", tol=1e-6)[0]
+    X2 = run_plan(w, gpu, precision="fp32", tol=1e-6)[0]
+    assert np.array_equal(X1, X2)
+
+
+# ----------------------------------------------------------------- ragged ----
+
+def test_ragged_batch_auto_precision(gpu):
+    say("ragged auto")
+    w = synth.ragged_batch(n_inst=30, seed=12)
+    Xr, off, ok = oracle.spectra(w)
+    X, P, valid, off_g, cls = run_plan(w, gpu, precision="auto")
+    assert np.array_equal(off, off_g)
+    say(f"  classes: {[(c.fp64, c.w, c.n, c.parts) for c in cls]}")
+    for i in range(w.n_inst):
+        if not ok[i]:
+            continue
+        t = w.inst_tol[i]
+        bound = max(t, FP32_SPEC) if t >= 1e-6 else max(t, 1e-11)
+        e = rel(X[off[i]:off[i + 1]], Xr[off[i]:off[i + 1]])
+        assert e <= bound, (i, t, e, w.seg_len[w.inst_seg[i]], w.n_bins[i])
+
+
+# ------------------------------------------------------------- edge cases ----
+
+@pytest.mark.parametrize("L,K,mc", [(1, 3, 1e-2), (5, 8, 3e-2), (63, 17, 1e-2), (64, 16, 5e-4),
+                                    (65, 9, 1e-1), (130, 40, 2e-2), (1000, 1, 1e-2), (257, 101, 0.0)])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_small_and_ragged_sizes(gpu, L, K, mc, prec):
+    say(f"edge L={L} K={K} mc={mc} {prec}")
+    w = synth.random_small(L + K, L, K, mc, f0=50.0, fs=64.0, t_start=3.0)
+    Xr, off, ok = oracle.spectra(w)
+    X, P, valid, _, _ = run_plan(w, gpu, precision=prec, tol=1e-6 if prec == "fp32" else 1e-10)
+    assert valid[0] == ok[0] == 1
+    assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_complex_strain(gpu, prec):
+    say(f"complex strain {prec}")
+    w = synth.random_small(3, 3000, 64, 2e-2, f0=45.0, fs=128.0, complex_strain=True)
+    Xr, off, ok = oracle.spectra(w)
+    X, _, _, _, _ = run_plan(w, gpu, precision=prec, tol=1e-6 if prec == "fp32" else 1e-10)
+    assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
+
+
+def test_identity_map_equals_fft(gpu):
+    say("identity = fft")
+    L, fs = 512, 128.0
+    x = np.random.default_rng(21).standard_normal(L)
+    w = synth.pure_tone(L=L, fs=fs, f_lo=0.0, df=fs / L, K=L)
+    w.strain = x
+    X, _, _, _, _ = run_plan(w, gpu, precision="fp64", tol=1e-11)
+    assert rel(X, np.fft.fft(x)) <= FP64_SPEC
+
+
+@pytest.mark.parametrize("parts", [1, 2, 4])
+@pytest.mark.parametrize("sigma", [1.25, 2.0, 3.0])
+def test_parts_and_upsampling(gpu, parts, sigma):
+    say(f"parts={parts} sigma={sigma}")
+    w = synth.single_segment()
+    Xr, _, _ = oracle.spectra(w)
+    X, _, _, _, cls = run_plan(w, gpu, precision="fp64", tol=1e-9, parts=parts, sigma=sigma)
+    assert cls[0].parts == parts
+    assert rel(X, Xr) <= FP64_SPEC
+
+
+def test_invalid_instances_are_zero_and_flagged(gpu):
+    say("invalid instances")
+    w = synth.semicoherent(hours=0.5, n_mc=3, n_sub=2, seed=9)
+    w.mc = np.array([1e-1, 1e-1, 8e-2, 8e-2, 5e-4, 5e-4])    # heavy templates coalesce early
+    idx = np.arange(0, w.n_inst, 7)
+    sub = w.subset(idx)
+    Xr, off, ok = oracle.spectra(sub)
+    assert ok.sum() < len(ok) and ok.sum() > 0
+    X, P, valid, _, _ = run_plan(sub, gpu, precision="fp32", tol=1e-6)
+    assert np.array_equal(valid, ok)
+    errs = per_instance_errors(X, Xr, off, ok)
+    assert errs.max() <= FP32_SPEC

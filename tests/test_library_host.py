@@ -1,0 +1,148 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library loads, exports every function the public headers declare, and
+rejects bad arguments before touching a device; the host parameter math
+(kernel width, grid size, ES Fourier transform, beta) is checked against
+independent references.
+"""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import paper_2609_12476_amd as pkg
+from paper_2609_12476_amd import nufft_resample as nr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b([a-z_][a-z0-9_]*)\s*\(", src):
+            name = m.group(1)
+            if name.startswith(("nufft_resample_", "nr_mlp_")):
+                names.add(name)
+    return names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = ctypes.CDLL(nr.LIB_PATH)
+    names = declared_functions()
+    assert "nufft_resample_plan" in names and "nufft_resample_execute" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _segs(n=2, L=7680, fs=256.0):
+    return nr.make_segments(np.arange(n) * L, [L] * n, [fs] * n, np.arange(n) * 30.0)
+
+
+def _tmpls(mc=(1e-2,), K=30):
+    m = len(mc)
+    return nr.make_templates(mc, [50.0] * m, [49.5] * m, [1 / 30] * m, [K] * m, [60.0] * m)
+
+
+def _opt(**kw):
+    o = nr.nufft_resample_default_options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@pytest.mark.parametrize("case,code", [
+    ("tol_zero", nr.NR_ERR_INVALID_ARG), ("tol_big", nr.NR_ERR_INVALID_ARG),
+    ("no_segs", nr.NR_ERR_INVALID_ARG), ("bad_fs", nr.NR_ERR_INVALID_ARG),
+    ("neg_mc", nr.NR_ERR_INVALID_ARG), ("nan_mc", nr.NR_ERR_INVALID_ARG),
+    ("zero_bins", nr.NR_ERR_INVALID_ARG), ("bad_inst", nr.NR_ERR_INVALID_ARG),
+    ("bad_sigma", nr.NR_ERR_INVALID_ARG), ("bad_parts", nr.NR_ERR_INVALID_ARG),
+    ("past_strain", nr.NR_ERR_INVALID_ARG), ("fp32_strict", nr.NR_ERR_TOL_UNATTAINABLE),
+    ("fp64_strict", nr.NR_ERR_TOL_UNATTAINABLE), ("huge_grid", nr.NR_ERR_INVALID_ARG),
+    ("bad_precision", nr.NR_ERR_INVALID_ARG)])
+def test_plan_rejects_bad_arguments_before_device_work(case, code):
+    segs, tmpls, inst, tol, opt = _segs(), _tmpls(), None, 1e-6, _opt()
+    if case == "tol_zero":
+        tol = 0.0
+    elif case == "tol_big":
+        tol = 0.5
+    elif case == "no_segs":
+        segs = (nr.NrSegment * 0)()
+    elif case == "bad_fs":
+        segs[1].fs = 0.0
+    elif case == "neg_mc":
+        tmpls[0].mc_msun = -1.0
+    elif case == "nan_mc":
+        tmpls[0].mc_msun = float("nan")
+    elif case == "zero_bins":
+        tmpls[0].n_bins = 0
+    elif case == "bad_inst":
+        inst = nr.make_instances([0, 2], [0, 0])
+    elif case == "bad_sigma":
+        opt.sigma = 0.9
+    elif case == "bad_parts":
+        opt.parts = 3
+    elif case == "past_strain":
+        opt.strain_length = 7680
+    elif case == "fp32_strict":
+        opt.strict, tol = 1, 1e-9
+    elif case == "fp64_strict":
+        opt.strict, opt.precision, tol = 1, nr.NR_FP64, 1e-14
+    elif case == "huge_grid":
+        tmpls = _tmpls(K=4000)
+    elif case == "bad_precision":
+        opt.precision = 7
+    with pytest.raises(nr.NrError) as e:
+        nr.nufft_resample_plan(segs, tmpls, inst, tol, opt)
+    assert e.value.code == code
+    assert nr.nufft_resample_last_error(None)
+
+
+def test_null_plan_calls_fail_cleanly():
+    lib = nr.load()
+    assert lib.nufft_resample_execute(None, None, None, None, None) == nr.NR_ERR_INVALID_ARG
+    assert lib.nufft_resample_semicoherent_sum(None, None, None, None, None) == nr.NR_ERR_INVALID_ARG
+    lib.nufft_resample_destroy(None)
+
+
+def test_kernel_width_tracks_tolerance():
+    ws = [pkg.nufft_resample_kernel_params(t, precision="fp64").w for t in
+          (1e-2, 1e-3, 1e-4, 1e-6, 1e-8, 1e-9, 1e-11)]
+    assert ws == sorted(ws) and ws[0] >= 2 and ws[-1] <= 16
+    assert pkg.nufft_resample_kernel_params(1e-6).w == 8
+    assert pkg.nufft_resample_kernel_params(1e-9, precision="auto").fp64 == 1
+    assert pkg.nufft_resample_kernel_params(1e-6, precision="auto").fp64 == 0
+
+
+@pytest.mark.parametrize("K,n", [(30, 60), (600, 1200), (200, 400), (1200, 2400), (7, 16), (1, 16)])
+def test_grid_size_is_smallest_smooth_number(K, n):
+    p = pkg.nufft_resample_kernel_params(1e-6, 2.0, "fp32", K)
+    assert p.n == n
+    prod = 1
+    for r in p.radix[:p.n_radix]:
+        assert r in (2, 3, 4, 5)
+        prod *= r
+    assert prod == p.n
+
+
+@pytest.mark.parametrize("w", [4, 8, 11, 14])
+def test_kernel_fourier_transform_matches_adaptive_quadrature(w):
+    beta = 2.30 * w
+    h = w / 2
+    for xi in (0.0, 0.3, 1.0, math.pi / 2, 2.5):
+        f = lambda x: math.exp(beta * (math.sqrt(max(0.0, 1 - (x / h) ** 2)) - 1)) * math.cos(xi * x)
+        ref, _ = integrate.quad(f, -h, h, epsabs=1e-15, epsrel=1e-13, limit=400)
+        got = pkg.nufft_resample_kernel_ft(w, beta, xi)
+        assert abs(got - ref) <= 1e-11 * abs(ref)
+
+
+def test_chirp_beta_matches_oracle():
+    for mc, f0 in [(5e-4, 40.0), (1e-2, 50.0), (1e-1, 60.0), (3e-3, 41.5)]:
+        assert pkg.nufft_resample_chirp_beta(mc, f0) == pytest.approx(oracle.beta(mc, f0), rel=1e-15)
