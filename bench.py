@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Throughput of batched semicoherent NUFFT resampling on one MI355X.
+
+One step = one semicoherent sum over the whole workload: for every
+(segment, template) instance the resampled times, the spreading, the FFT,
+the deconvolution, the power and the per-template segment sum, all in the
+gfx950 kernels (FP64 tau and phase reduction, FP32 spreading/FFT/power).
+
+Workload (default): 1 h of 256 Hz white Gaussian noise with one injected
+0PN chirp, split into 120 segments of 30 s; 64 chirp-mass templates
+log-spaced over [5e-4, 1e-1] Msun x 20 sub-bands of 1 Hz over 40-60 Hz;
+spreading tolerance 1e-6, 2x upsampled grid: 153,600 instances.
+
+Prints one JSON line.  Outside the timed region it also
+  - checks the FP32 spectra of every instance against the FP64 path
+    (tolerance 1e-10) and the summed statistic,
+  - times the plain FP64 path (same kernels, FP64 class, same tolerance),
+  - times the oracle on a bounded seeded sample of instances on the host
+    cores and checks the GPU spectra of that sample against it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("segment×template spectra/s at ≤1e-5 rel err vs FP64 plain; "
+          "spread+FFT HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+# VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (one FP32 or FP64 FMA per lane per cycle without packed FP32).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--method", default="fused", choices=["fused", "staged"])
+    ap.add_argument("--hours", type=float, default=1.0)
+    ap.add_argument("--n-mc", type=int, default=64)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=768,
+                    help="instances timed on the oracle (seeded sample)")
+    ap.add_argument("--copy-mib", type=int, default=256,
+                    help="size of the plain copy kernel run once for counter calibration")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_ops(classes):
+    """VALU lane-operations the fused spreader needs, by the per-sample op model:
+    tau series (degree + 1 FMAs; 40 for the log1p/expm1 form) + 6 for the two
+    products and reductions mod 1, 2 to split the grid position, 13 for the
+    sin/cos pair, 2 for the heterodyne product and 3D + 1 for the Chebyshev
+    moments of degree D."""
+    tot = 0
+    for c in classes:
+        series = c.series_terms + (c.n_points - c.fallback_points) + 40 * c.fallback_points
+        tot += series + c.n_points * (6 + 2 + 13 + 2 + 3 * c.degree + 1)
+    return tot
+
+
+def time_steps(plan, x, stat, used, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        stat.zero_()
+        used.zero_()
+        plan.semicoherent_sum(x, None, stat, used)
+    torch.cuda.synchronize()
+    plan.stage_times()  # reset the per-stage accumulation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stat.zero_()
+        used.zero_()
+        plan.semicoherent_sum(x, None, stat, used)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, plan.stage_times()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(sharding by template is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_2609_12476_amd import Plan, complex_view
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log("generating workload")
+    w = synth.semicoherent(hours=args.hours, n_mc=args.n_mc, n_sub=20, seed=1, tol=1e-6)
+    w32 = w.as_float32_strain()           # the FP32 path's input values; the FP64 runs use the same
+    plan = Plan.from_workload(w32, tol=1e-6, precision="fp32", method=args.method, profile=True)
+    info = plan.info
+    cls = plan.classes()
+    x32 = plan.strain_tensor(w32.strain, dev)
+    stat = torch.zeros(info.stat_bins, dtype=torch.float32, device=dev)
+    used = torch.zeros(plan.n_tmpls, dtype=torch.int32, device=dev)
+    log(f"plan: {info.n_inst} instances, {info.n_valid} valid, classes "
+        f"{[(c.fp64, c.w, c.n, c.degree, c.parts) for c in cls]}, chunks {info.n_chunks}")
+
+    # copy kernel of known size, for scaling the memory counters
+    if args.copy_mib > 0:
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log("timing fp32")
+    el, st = time_steps(plan, x32, stat, used, args.steps, args.warmup)
+    ms_step = el / args.steps * 1e3
+    value = info.n_valid * args.steps / el
+    out = {
+        "metric": METRIC, "value": value, "unit": "spectra/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"semicoherent_{args.hours:g}h_{w.n_seg}seg_{args.n_mc}mc_x20subbands_256Hz",
+                   "instances": int(info.n_inst), "valid_instances": int(info.n_valid),
+                   "samples_per_segment": int(w.seg_len[0]), "bins_per_spectrum": 30,
+                   "tol": 1e-6, "sigma": 2.0, "method": args.method, "kernel_width": cls[0].w,
+                   "grid": cls[0].n, "degree": cls[0].degree, "parallelism": "single_gpu"},
+        "all_instance_rate": info.n_inst * args.steps / el,
+    }
+    stage_ms = {k: v[0] / args.steps for k, v in st.items()}
+    out["stage_ms_per_step"] = stage_ms
+
+    # roofline of the dominant kernel
+    dom = max(("tau", "spread", "epilogue"), key=lambda k: stage_ms[k])
+    launches = st[dom][1] / args.steps
+    per_launch_ms = stage_ms[dom] / max(launches, 1)
+    n = cls[0].n
+    pts = info.valid_points
+    if dom == "spread" and args.method == "staged":
+        bytes_step = pts * 8 + info.n_valid * n * 8           # point stream in, grid out
+        achieved = bytes_step / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9
+        roof = {"kernel": "spread_kernel<float>", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None}
+    elif dom == "tau":
+        bytes_step = pts * 8
+        achieved = bytes_step / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9
+        roof = {"kernel": "tau_kernel<float>", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None}
+    elif dom == "spread":
+        ops = algorithmic_ops(cls)
+        achieved = ops / max(launches, 1) / (per_launch_ms * 1e-3) / 1e12
+        roof = {"kernel": "spread_kernel<float, fused>", "bound": "alu", "achieved": achieved,
+                "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": None, "ops_per_point": ops / pts}
+    else:
+        bytes_step = info.n_valid * n * 8 + info.stat_bins * 8
+        achieved = bytes_step / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9
+        roof = {"kernel": "epilogue_sum_kernel<float>", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None}
+    roof["avg_launch_ms"] = per_launch_ms
+    out["roofline"] = roof
+    # spread + FFT HBM figure of the metric: algorithmic bytes of the spread and
+    # FFT/epilogue kernels over their summed time
+    sf_bytes = (pts * 8 if args.method == "staged" else 0) + 2 * info.n_valid * n * 8 + info.stat_bins * 8
+    out["spread_fft_hbm_gbs"] = sf_bytes / ((stage_ms["spread"] + stage_ms["epilogue"]) * 1e-3) / 1e9
+
+    # accuracy: FP32 vs the FP64 path on every instance
+    if not args.no_check:
+        log("accuracy check vs fp64")
+        sp32, _, valid = plan.execute(x32, want=("spectra", "valid"))
+        p64 = Plan.from_workload(w32, tol=1e-10, precision="fp64", method=args.method)
+        x64 = p64.strain_tensor(w32.strain, dev)
+        sp64, _, _ = p64.execute(x64, want=("spectra",))
+        s64, u64 = p64.semicoherent_sum(x64)
+        stat.zero_(); used.zero_()
+        plan.semicoherent_sum(x32, None, stat, used)
+        torch.cuda.synchronize()
+        K = 30
+        a = complex_view(sp32).to(torch.complex128).view(-1, K)
+        b = complex_view(sp64).view(-1, K)
+        v = valid.bool()
+        num = torch.linalg.vector_norm(a - b, dim=1)[v]
+        den = torch.linalg.vector_norm(b, dim=1)[v]
+        e = (num / den).cpu().numpy()
+        sa = stat.double().view(-1, K)
+        sb = s64.view(-1, K)
+        keep = u64 > 0
+        es = (torch.linalg.vector_norm(sa - sb, dim=1)[keep] /
+              torch.linalg.vector_norm(sb, dim=1)[keep]).cpu().numpy()
+        out["accuracy"] = {"spectra_rel_l2_max": float(e.max()), "spectra_rel_l2_median": float(np.median(e)),
+                           "stat_rel_l2_max": float(es.max()), "reference": "gpu fp64 path, tol 1e-10",
+                           "n_used_equal": bool(torch.equal(used, u64))}
+        del sp32, sp64, a, b, p64, x64
+        torch.cuda.empty_cache()
+
+    # the plain FP64 path at the same tolerance
+    if not args.no_fp64:
+        log("timing fp64")
+        p64 = Plan.from_workload(w32, tol=1e-6, precision="fp64", method=args.method, profile=True)
+        x64 = p64.strain_tensor(w32.strain, dev)
+        s64 = torch.zeros(p64.info.stat_bins, dtype=torch.float64, device=dev)
+        u64 = torch.zeros(p64.n_tmpls, dtype=torch.int32, device=dev)
+        el64, st64 = time_steps(p64, x64, s64, u64, max(3, args.steps // 2), 1)
+        v64 = p64.info.n_valid * max(3, args.steps // 2) / el64
+        out["fp64_value"] = v64
+        out["speedup_vs_fp64"] = value / v64
+        out["fp64_stage_ms_per_step"] = {k: v[0] / max(3, args.steps // 2) for k, v in st64.items()}
+        p64.close()
+
+    # oracle on a bounded seeded sample of instances, on the host cores
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline (oracle)")
+        rng = np.random.default_rng(123)
+        ok_mask = plan.valid_mask().astype(bool)
+        cand = np.flatnonzero(ok_mask)
+        idx = np.sort(rng.choice(cand, size=min(args.cpu_sample, len(cand)), replace=False))
+        t0 = time.perf_counter()
+        Xr, off, ok = oracle.spectra(w32, inst_idx=idx)
+        t1 = time.perf_counter()
+        out["cpu_baseline"] = {"value": len(idx) / (t1 - t0), "unit": "spectra/s",
+                               "cores": int(oracle.num_threads()), "kind": "oracle",
+                               "sample": f"{len(idx)} seeded valid instances of the {info.n_inst} "
+                                         f"(direct long-double sums, {w.seg_len[0]} samples x 30 bins each)",
+                               "seconds": t1 - t0}
+        sp32, _, _ = plan.execute(x32, want=("spectra",))
+        torch.cuda.synchronize()
+        X = complex_view(sp32).cpu().numpy().astype(np.complex128)
+        boff = plan.bin_offsets()
+        errs = []
+        for j, i in enumerate(idx):
+            g = X[boff[i]:boff[i + 1]]
+            r = Xr[off[j]:off[j + 1]]
+            errs.append(np.linalg.norm(g - r) / np.linalg.norm(r))
+        out["oracle_check"] = {"instances": len(idx), "spectra_rel_l2_max": float(np.max(errs))}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -117,6 +117,8 @@ typedef struct {
     int32_t strict;             /* 1: unattainable tolerances are errors, not clamped */
     int32_t check_finite;       /* 1: execute scans the strain and synchronises */
     int32_t parts;              /* waves per instance in the spreader; 0: automatic */
+    int32_t profile;            /* 1: time every kernel launch with HIP events */
+    int32_t reserved;
     int64_t strain_length;      /* samples in the strain array; 0: not checked */
     int64_t max_workspace_bytes;/* device workspace cap; 0: 8 GiB */
     void* stream;               /* hipStream_t of every enqueue; NULL: the null stream */
@@ -147,7 +149,23 @@ typedef struct {
     double beta_es;     /* ES shape parameter */
     int64_t n_inst;     /* valid instances in the class */
     int64_t n_points;   /* sum of L over them */
+    int64_t series_terms;    /* sum over instances of L x (degree of the tau series) */
+    int64_t fallback_points; /* samples of instances using the log1p/expm1 form of tau */
 } nr_class_info;
+
+/* Kernel time per stage, accumulated over launches since the last read. */
+typedef enum {
+    NR_STAGE_LAYOUT = 0,   /* lane-major strain copy */
+    NR_STAGE_TAU = 1,      /* point stream (staged method) */
+    NR_STAGE_SPREAD = 2,   /* spreading (fused method: tau + spreading) */
+    NR_STAGE_EPILOGUE = 3, /* FFT, deconvolution, power / segment sum, invalid fill */
+    NR_N_STAGES = 4
+} nr_stage;
+
+typedef struct {
+    double ms[NR_N_STAGES];       /* summed kernel durations in milliseconds */
+    int64_t launches[NR_N_STAGES];/* kernel launches timed */
+} nr_stage_times;
 
 /* Default options: NR_FP32, NR_METHOD_AUTO, sigma 2, real strain, non-strict. */
 void nufft_resample_default_options(nr_options* opt);
@@ -193,6 +211,13 @@ nr_status nufft_resample_execute(nr_plan p, const void* strain, void* spectra, v
 nr_status nufft_resample_semicoherent_sum(nr_plan p, const void* strain,
                                           const double* seg_weight, void* stat,
                                           int32_t* n_used);
+
+/*
+ * Per-stage kernel times of a plan created with profile = 1: waits for the
+ * recorded launches to finish (synchronising), returns their summed
+ * durations and starts a new accumulation.  All zeros when profiling is off.
+ */
+nr_status nufft_resample_stage_times(nr_plan p, nr_stage_times* out);
 
 /* Plan summary. */
 nr_status nufft_resample_query(nr_plan p, nr_plan_info* info);

@@ -39,6 +39,7 @@ def lib():
         L.nro_beta.restype = ctypes.c_double
         L.nro_beta.argtypes = [ctypes.c_double, ctypes.c_double]
         L.nro_t_sun.restype = ctypes.c_double
+        L.nro_num_threads.restype = ctypes.c_int
         L.nro_dtau.argtypes = [ctypes.c_double] * 4 + [ctypes.c_int64, P]
         L.nro_valid.restype = ctypes.c_int
         L.nro_valid.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int64]
@@ -64,6 +65,10 @@ def _strain(x):
 
 def beta(mc_msun, f0):
     return lib().nro_beta(float(mc_msun), float(f0))
+
+
+def num_threads():
+    return lib().nro_num_threads()
 
 
 def t_sun():

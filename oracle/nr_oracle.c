@@ -30,6 +30,7 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <omp.h>
 #include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -58,6 +59,8 @@ static q_t beta_q(double mc_msun, double f0)
 double nro_beta(double mc_msun, double f0) { return (double)beta_q(mc_msun, f0); }
 
 double nro_t_sun(void) { return (double)t_sun_q(); }
+
+int nro_num_threads(void) { return omp_get_max_threads(); }
 
 /* tau(t) of Eq. (new_t) (t relative to t0). */
 static q_t tau_q(q_t beta, q_t t)

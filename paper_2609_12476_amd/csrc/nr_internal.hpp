@@ -58,6 +58,7 @@ struct SpreadArgs {
     const double* coef;      // Horner coefficients
     const void* taps;        // [w][deg+1] Chebyshev coefficients of the per-cell kernel pieces
     const void* strain_lm;   // lane-major strain copy of the class (real or complex)
+    const void* phase_table; // exp(2 pi i k / N), k < N (N = phase_table_size)
     void* points;            // staged point stream (chunk-relative)
     void* grid;              // [chunk instances][n] complex
     int64_t first;           // first class instance of the chunk
@@ -110,6 +111,8 @@ hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,
 hipError_t launch_finite_scan(const void* strain, int64_t n, int fp64, int32_t* flag,
                               hipStream_t st);
 size_t spread_lds_bytes(int fp64, int n);
+int phase_table_size(int fp64);
+constexpr int kHornerPad = 16;   // zero coefficients appended to every class's tau series
 size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode);
 
 }  // namespace nr

@@ -48,57 +48,114 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 // ------------------------------------------------------------------ tau --
 
+constexpr int kHornerFast = 16;   // tau series degrees evaluated from registers
+
+// Resampling constants of the wave's instance, loaded once per wave
+// (uniform, so they live in scalar registers).
+struct TauConsts {
+    double a, c, df, fc, hn;
+    int ndeg, L;
+    const double* b;               // Horner coefficients (global; zero padded)
+    double bc[kHornerFast];
+};
+
+__device__ __forceinline__ void load_tau(TauConsts& t, const InstDev& d,
+                                         const double* __restrict__ coef, double hn)
+{
+    t.a = d.a;
+    t.c = d.c;
+    t.df = d.df;
+    t.fc = d.fc;
+    t.hn = hn;
+    t.ndeg = d.ndeg;
+    t.L = d.L;
+    t.b = coef + d.coef_off;
+#pragma unroll
+    for (int k = 0; k < kHornerFast; ++k) t.bc[k] = t.b[k];  // the array carries kHornerFast zeros of padding
+}
+
+template <int N>
+__device__ __forceinline__ double horner(const double* b, double x)
+{
+    double acc = b[N - 1];
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) acc = fma(acc, x, b[k]);
+    return acc * x;
+}
+
 // dtau_j = tau(t_s + j/fs) - tau(t_s) of Eq. (new_t).  With
-// y = (8/3) beta j / (u_s fs), dtau = a (1 - (1 - y)^{5/8}); the series in y
-// is a polynomial in j whose coefficients the plan stores per instance
-// (Horner in FP64); instances whose series converges too slowly use
+// y = (8/3) beta j / (u_s fs), dtau = a (1 - (1 - y)^{5/8}); the binomial
+// series in y is a polynomial in j whose coefficients the plan stores per
+// instance (Horner in FP64); instances whose series converges too slowly use
 // a * (-expm1((5/8) log1p(-y))).  Both forms avoid the cancellation of the
 // direct difference of two values of size 3/(5 beta).
-__device__ __forceinline__ double dtau_of(const InstDev& d, const double* __restrict__ coef,
-                                          int64_t j)
+__device__ __forceinline__ double dtau_of(const TauConsts& t, int j)
 {
     const double jd = (double)j;
-    if (d.ndeg == 0) return jd * d.c;
-    if (d.ndeg > 0) {
-        const double* b = coef + d.coef_off;
-        double acc = b[d.ndeg - 1];
-        for (int k = d.ndeg - 2; k >= 0; --k) acc = fma(acc, jd, b[k]);
+    switch (t.ndeg) {
+    case 0: return jd * t.c;
+#define NR_H(N) \
+    case N: return horner<N>(t.bc, jd);
+        NR_H(1) NR_H(2) NR_H(3) NR_H(4) NR_H(5) NR_H(6) NR_H(7) NR_H(8) NR_H(9) NR_H(10) NR_H(11)
+        NR_H(12) NR_H(13) NR_H(14) NR_H(15) NR_H(16)
+#undef NR_H
+    default:
+        break;
+    }
+    if (t.ndeg > 0) {
+        double acc = t.b[t.ndeg - 1];
+        for (int k = t.ndeg - 2; k >= 0; --k) acc = fma(acc, jd, t.b[k]);
         return acc * jd;
     }
-    return d.a * (-expm1(0.625 * log1p(-d.c * jd)));
+    return t.a * (-expm1(0.625 * log1p(-t.c * jd)));
 }
 
-// frac(x) as a 32-bit fixed-point fraction of one period, rounded to nearest.
-__device__ __forceinline__ uint32_t frac_u32(double x)
+// The two reductions modulo one period, in FP64:
+//   pos   = frac(df dtau - w/(2n))  (grid position of the support's start, in periods)
+//   phase = frac(fc dtau)           (heterodyne phase, in cycles)
+struct Reduced {
+    double pos, phase;
+};
+
+__device__ __forceinline__ Reduced reduce_point(const TauConsts& t, int j)
 {
-    double f = x - floor(x);
-    double y = rint(f * 4294967296.0);
-    y = (y >= 4294967296.0) ? 0.0 : y;
-    return (uint32_t)y;
+    const double dt = dtau_of(t, j);
+    Reduced r;
+    r.pos = __builtin_amdgcn_fract(fma(t.df, dt, -t.hn));
+    r.phase = __builtin_amdgcn_fract(t.fc * dt);
+    return r;
 }
 
-__device__ __forceinline__ double frac_f64(double x) { return x - floor(x); }
+// 32-bit fixed-point fraction of a value in [0, 1) (truncating).
+__device__ __forceinline__ uint32_t to_u32(double f) { return (uint32_t)ldexp(f, 32); }
 
 template <typename T>
-__device__ __forceinline__ typename PointOf<T>::type make_point(const InstDev& d,
-                                                                const double* __restrict__ coef,
-                                                                int64_t j);
-
+__device__ __forceinline__ typename PointOf<T>::type pack_point(Reduced r);
 template <>
-__device__ __forceinline__ uint2 make_point<float>(const InstDev& d,
-                                                   const double* __restrict__ coef, int64_t j)
+__device__ __forceinline__ uint2 pack_point<float>(Reduced r)
 {
-    const double dt = dtau_of(d, coef, j);
-    return make_uint2(frac_u32(d.df * dt), frac_u32(d.fc * dt));
+    return make_uint2(to_u32(r.pos), to_u32(r.phase));
+}
+template <>
+__device__ __forceinline__ double2 pack_point<double>(Reduced r)
+{
+    return make_double2(r.pos, r.phase);
 }
 
+template <typename T>
+__device__ __forceinline__ Reduced unpack_point(typename PointOf<T>::type p);
 template <>
-__device__ __forceinline__ double2 make_point<double>(const InstDev& d,
-                                                      const double* __restrict__ coef, int64_t j)
+__device__ __forceinline__ Reduced unpack_point<float>(uint2 p)
 {
-    const double dt = dtau_of(d, coef, j);
-    return make_double2(frac_f64(d.df * dt), frac_f64(d.fc * dt));
+    return Reduced{ldexp((double)p.x, -32), ldexp((double)p.y, -32)};
 }
+template <>
+__device__ __forceinline__ Reduced unpack_point<double>(double2 p)
+{
+    return Reduced{p.x, p.y};
+}
+
+__device__ __forceinline__ double half_width_periods(int w, int n) { return 0.5 * (double)w / (double)n; }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void tau_kernel(SpreadArgs a)
@@ -111,14 +168,16 @@ __global__ __launch_bounds__(kBlock) void tau_kernel(SpreadArgs a)
     if (item >= a.count) return;
     const int part = wave % parts;
     const InstDev d = a.inst[a.first + item];
+    TauConsts tc;
+    load_tau(tc, d, a.coef, half_width_periods(a.w, a.n));
     const int C = d.C;
-    const int64_t v = (int64_t)part * kWave + lane;
+    const int v = part * kWave + lane;
     P* out = reinterpret_cast<P*>(a.points) + (d.pt_off - a.pt_base) + (int64_t)part * C * kWave + lane;
     for (int s = 0; s < C; ++s) {
-        const int64_t j = v * C + s;
+        const int j = v * C + s;
         P pt;
         if (j < d.L) {
-            pt = make_point<T>(d, a.coef, j);
+            pt = pack_point<T>(reduce_point(tc, j));
         } else {
             pt.x = 0;
             pt.y = 0;
@@ -129,74 +188,61 @@ __global__ __launch_bounds__(kBlock) void tau_kernel(SpreadArgs a)
 
 // --------------------------------------------------------------- spread --
 
-// sin and cos of 2 pi R / 2^32: exact octant reduction of the fixed-point
-// phase, then Taylor polynomials on [0, pi/4] (truncation < 3e-8).
-__device__ __forceinline__ void sincos_turn_u32(uint32_t R, float& s, float& c)
-{
-    const uint32_t o = R >> 29;
-    uint32_t rem = R & 0x1FFFFFFFu;
-    if (o & 1u) rem = 0x20000000u - rem;
-    const float th = (float)rem * 1.4629180792671596e-09f;  // 2 pi / 2^32
-    const float t2 = th * th;
-    float sn = fmaf(t2, 2.7557319e-06f, -1.9841270e-04f);
-    sn = fmaf(t2, sn, 8.3333333e-03f);
-    sn = fmaf(t2, sn, -1.6666667e-01f);
-    sn = fmaf(t2 * th, sn, th);
-    float cs = fmaf(t2, 2.4801587e-05f, -1.3888889e-03f);
-    cs = fmaf(t2, cs, 4.1666667e-02f);
-    cs = fmaf(t2, cs, -0.5f);
-    cs = fmaf(t2, cs, 1.0f);
-    const bool swap = ((o + 1u) >> 1) & 1u;
-    float cc = swap ? sn : cs;
-    float ss = swap ? cs : sn;
-    c = (((o + 2u) >> 2) & 1u) ? -cc : cc;
-    s = ((o >> 2) & 1u) ? -ss : ss;
-}
+// exp(2 pi i k / N) for k < N, the coarse part of the heterodyne phasor.
+template <typename T>
+struct PhaseTable;
+template <>
+struct PhaseTable<float> {
+    static constexpr int bits = 10;   // 1024 entries; fine angle |theta| <= pi/1024
+};
+template <>
+struct PhaseTable<double> {
+    static constexpr int bits = 8;    // 256 entries; fine angle |theta| <= pi/256
+};
 
 // Decoded point: first grid cell g of its support (in [1, n]), the
 // Chebyshev variable u = 2 (g - (x - w/2)) - 1 in (-1, 1], and the
-// heterodyned strength (cr, ci) = x_j exp(-2 pi i r_j).
+// heterodyned strength (cr, ci) = x_j exp(-2 pi i phase).
 template <typename T>
 struct Decoded {
     int g;
     T u, cr, ci;
 };
 
-template <typename T>
-__device__ __forceinline__ Decoded<T> decode(typename PointOf<T>::type p, T xr, T xi, int n,
-                                             int w);
-
-template <>
-__device__ __forceinline__ Decoded<float> decode<float>(uint2 p, float xr, float xi, int n, int w)
+template <typename T, bool CPLX>
+__device__ __forceinline__ Decoded<T> decode(Reduced r, T xr, T xi, int n, const cpx<T>* tab)
 {
-    Decoded<float> o;
-    const uint64_t X = (uint64_t)p.x * (uint32_t)n;         // position in 2^-32 cells
-    const uint64_t hq = (uint64_t)(uint32_t)w << 31;        // w/2 cells
-    uint64_t S = X - hq;
-    if (X < hq) S += (uint64_t)(uint32_t)n << 32;
-    o.g = (int)(S >> 32) + 1;
-    o.u = 1.0f - (float)(uint32_t)S * 4.656612873077393e-10f;  // 2^-31
-    float sn, cs;
-    sincos_turn_u32(p.y, sn, cs);
-    o.cr = xr * cs + xi * sn;
-    o.ci = xi * cs - xr * sn;
-    return o;
-}
-
-template <>
-__device__ __forceinline__ Decoded<double> decode<double>(double2 p, double xr, double xi, int n,
-                                                          int w)
-{
-    Decoded<double> o;
-    double S = p.x * (double)n - 0.5 * (double)w;
-    if (S < 0.0) S += (double)n;
+    Decoded<T> o;
+    const double S = r.pos * (double)n;           // (x - w/2) mod n, in cells
     const double fl = floor(S);
-    o.g = min(max((int)fl + 1, 1), n);
-    o.u = 2.0 * ((fl + 1.0) - S) - 1.0;
-    double sn, cs;
-    sincospi(2.0 * p.y, &sn, &cs);
-    o.cr = xr * cs + xi * sn;
-    o.ci = xi * cs - xr * sn;
+    o.g = (int)fl + 1;
+    if (o.g > n) o.g -= n;  // S rounded up to n, which is cell position 0
+    o.u = (T)fma(-2.0, S - fl, 1.0);
+    // phase = k / N + theta / (2 pi), |theta| <= pi / N
+    constexpr int B = PhaseTable<T>::bits;
+    const double sc = r.phase * (double)(1 << B);
+    const double k = rint(sc);
+    const T th = (T)((sc - k) * (6.283185307179586476925 / (double)(1 << B)));
+    const cpx<T> e = tab[(int)k & ((1 << B) - 1)];
+    T cs, sn;
+    const T t2 = th * th;
+    if (sizeof(T) == 4) {
+        cs = fma(t2, T(-0.5), T(1));
+        sn = th;
+    } else {
+        cs = fma(t2, fma(t2, fma(t2, T(-1.0 / 720.0), T(1.0 / 24.0)), T(-0.5)), T(1));
+        sn = fma(th * t2, fma(t2, fma(t2, T(-1.0 / 5040.0), T(1.0 / 120.0)), T(-1.0 / 6.0)), th);
+    }
+    // exp(i 2 pi phase) = e * (cs + i sn); strength = x * conj(that)
+    const T er = e.x * cs - e.y * sn;
+    const T ei = e.y * cs + e.x * sn;
+    if (CPLX) {
+        o.cr = xr * er + xi * ei;
+        o.ci = xi * er - xr * ei;
+    } else {
+        o.cr = xr * er;
+        o.ci = -xr * ei;
+    }
     return o;
 }
 
@@ -271,18 +317,22 @@ __device__ __forceinline__ void flush(const Moments<T, D>& M, int g, const T* __
 // changes cell twice within a period).  Each wave owns its grid copy, so
 // the LDS additions of one grid come from one wave in program order and the
 // result does not depend on scheduling.
-template <typename T, int D, bool FUSED>
+template <typename T, int D, bool FUSED, bool CPLX>
 __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
 {
     using P = typename PointOf<T>::type;
+    constexpr int NT = 1 << PhaseTable<T>::bits;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* lds = tab + NT;
 
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int parts = a.parts;
     const int n = a.n, w = a.w;
     cpx<T>* grid = lds + wave * n;
+    const cpx<T>* gtab = reinterpret_cast<const cpx<T>*>(a.phase_table);
+    for (int k = threadIdx.x; k < NT; k += kBlock) tab[k] = gtab[k];
     for (int c = lane; c < n; c += kWave) grid[c] = cpx<T>{T(0), T(0)};
     __syncthreads();
 
@@ -293,9 +343,11 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
 
     if (item < a.count) {
         const InstDev d = a.inst[a.first + item];
+        TauConsts tc;
+        load_tau(tc, d, a.coef, half_width_periods(w, n));
         const int C = d.C;
         const int L = d.L;
-        const int64_t v = (int64_t)part * kWave + lane;
+        const int v = part * kWave + lane;
         const int64_t row0 = (int64_t)part * C * kWave + lane;
         const P* __restrict__ pts =
             FUSED ? nullptr
@@ -308,15 +360,15 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
         Sv.zero();
         int g_cur = -1, g_pend = -1;
         for (int s = 0; s < C; ++s) {
-            const int64_t j = v * C + s;
+            const int j = v * C + s;
             if (j < L) {
-                P pt;
+                Reduced r;
                 if (FUSED)
-                    pt = make_point<T>(d, a.coef, j);
+                    r = reduce_point(tc, j);
                 else
-                    pt = pts[(int64_t)s * kWave];
+                    r = unpack_point<T>(pts[(int64_t)s * kWave]);
                 T xr, xi;
-                if (a.strain_complex) {
+                if (CPLX) {
                     const cpx<T> xv = reinterpret_cast<const cpx<T>*>(a.strain_lm)[xs0 + (int64_t)s * kWave];
                     xr = xv.x;
                     xi = xv.y;
@@ -324,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
                     xr = reinterpret_cast<const T*>(a.strain_lm)[xs0 + (int64_t)s * kWave];
                     xi = T(0);
                 }
-                const Decoded<T> q = decode<T>(pt, xr, xi, n, w);
+                const Decoded<T> q = decode<T, CPLX>(r, xr, xi, n, tab);
                 if (q.g != g_cur) {
                     if (g_cur >= 0) {
                         if (g_pend >= 0) flush<T, D>(Sv, g_pend, A, grid, n, w);
@@ -649,7 +701,14 @@ static void allow_lds(K* kernel, size_t bytes)
 
 size_t spread_lds_bytes(int fp64, int n)
 {
-    return (size_t)4 * n * (fp64 ? 16 : 8);
+    const size_t csize = fp64 ? 16 : 8;
+    const size_t table = fp64 ? (size_t(1) << PhaseTable<double>::bits) : (size_t(1) << PhaseTable<float>::bits);
+    return (table + (size_t)4 * n) * csize;
+}
+
+int phase_table_size(int fp64)
+{
+    return fp64 ? (1 << PhaseTable<double>::bits) : (1 << PhaseTable<float>::bits);
 }
 
 size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode)
@@ -694,18 +753,25 @@ hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st)
     return hipGetLastError();
 }
 
+template <typename T, int D, bool FUSED, bool CPLX>
+static void launch_spread_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    allow_lds(spread_kernel<T, D, FUSED, CPLX>, lds);
+    spread_kernel<T, D, FUSED, CPLX><<<grid, dim3(kBlock), lds, st>>>(a);
+}
+
 template <typename T, int D>
 static hipError_t launch_spread_d(const SpreadArgs& a, int fused, hipStream_t st)
 {
     const int64_t per_block = 4 / a.parts;
-    dim3 grid((unsigned)((a.count + per_block - 1) / per_block)), block(kBlock);
+    dim3 grid((unsigned)((a.count + per_block - 1) / per_block));
     const size_t lds = spread_lds_bytes(sizeof(T) == 8, a.n);
     if (fused) {
-        allow_lds(spread_kernel<T, D, true>, lds);
-        spread_kernel<T, D, true><<<grid, block, lds, st>>>(a);
+        if (a.strain_complex) launch_spread_k<T, D, true, true>(a, grid, lds, st);
+        else launch_spread_k<T, D, true, false>(a, grid, lds, st);
     } else {
-        allow_lds(spread_kernel<T, D, false>, lds);
-        spread_kernel<T, D, false><<<grid, block, lds, st>>>(a);
+        if (a.strain_complex) launch_spread_k<T, D, false, true>(a, grid, lds, st);
+        else launch_spread_k<T, D, false, false>(a, grid, lds, st);
     }
     return hipGetLastError();
 }

@@ -1,0 +1,524 @@
+// gfx950 kernels of the learned proposal's network (see include/nr_mlp.h):
+// bfloat16 weight copies, fused three-layer forward, backward through the
+// activations, deterministic weight gradients, the loss, Adam, and the
+// region feature builder.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/nr_mlp.h"
+
+namespace {
+
+constexpr int IN = NR_MLP_IN, HID = NR_MLP_HIDDEN, NP = NR_MLP_PARAMS;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + HID * IN, OFF_W2 = OFF_B1 + HID,
+              OFF_B2 = OFF_W2 + HID * HID, OFF_W3 = OFF_B2 + HID, OFF_B3 = OFF_W3 + HID;
+static_assert(OFF_B3 + 1 == NP, "parameter layout");
+constexpr int RB = 32;     // rows per workgroup in the row-parallel kernels
+constexpr int BLK = 256;   // one thread per hidden unit
+
+thread_local std::string g_mlp_error;
+
+// ---------------------------------------------------------------- bf16 --
+
+typedef uint16_t bf16_t;
+
+__device__ __forceinline__ bf16_t to_bf16(float f)
+{
+    // round to nearest, ties to even
+    const uint32_t u = __float_as_uint(f);
+    return (bf16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Weight copies used by the products: W1t[k][j] = W1[j][k], W2t[k][j] =
+// W2[j][k] (column access by unit j is contiguous across threads), W2 as is
+// (for the backward product), w3.
+__global__ void refresh_bf16_kernel(const float* __restrict__ p, bf16_t* __restrict__ w1t,
+                                    bf16_t* __restrict__ w2, bf16_t* __restrict__ w2t,
+                                    bf16_t* __restrict__ w3)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < HID * IN) {
+        const int j = i / IN, k = i % IN;
+        w1t[k * HID + j] = to_bf16(p[OFF_W1 + i]);
+    }
+    if (i < HID * HID) {
+        const int j = i / HID, k = i % HID;
+        const bf16_t h = to_bf16(p[OFF_W2 + i]);
+        w2[i] = h;
+        w2t[k * HID + j] = h;
+    }
+    if (i < HID) w3[i] = to_bf16(p[OFF_W3 + i]);
+}
+
+// ------------------------------------------------------------- forward --
+
+// acc[r] += sum_k src[r][k] * wt[k][j] for the workgroup's RB rows; src in
+// LDS (row-major, width kw), wt bfloat16 [kw][HID] in global memory.
+template <int KW>
+__device__ __forceinline__ void rows_times_column(const float* __restrict__ src,
+                                                  const bf16_t* __restrict__ wt, int j,
+                                                  float (&acc)[RB])
+{
+    for (int k = 0; k < KW; k += 4) {
+        const float w0 = from_bf16(wt[(k + 0) * HID + j]);
+        const float w1 = from_bf16(wt[(k + 1) * HID + j]);
+        const float w2 = from_bf16(wt[(k + 2) * HID + j]);
+        const float w3 = from_bf16(wt[(k + 3) * HID + j]);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const float4 x = *reinterpret_cast<const float4*>(src + r * KW + k);
+            acc[r] = fmaf(x.x, w0, fmaf(x.y, w1, fmaf(x.z, w2, fmaf(x.w, w3, acc[r]))));
+        }
+    }
+}
+
+// One workgroup per RB rows, one thread per hidden unit j.
+__global__ __launch_bounds__(BLK) void forward_kernel(const float* __restrict__ x, int64_t B,
+                                                      const float* __restrict__ p,
+                                                      const bf16_t* __restrict__ w1t,
+                                                      const bf16_t* __restrict__ w2t,
+                                                      const bf16_t* __restrict__ w3,
+                                                      float* __restrict__ h1_out,
+                                                      float* __restrict__ h2_out,
+                                                      float* __restrict__ z_out)
+{
+    __shared__ __align__(16) float xs[RB * IN];
+    __shared__ __align__(16) float hs[RB * HID];
+    __shared__ float red[4][RB];
+    const int j = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int nr = (int)((B - r0) < RB ? (B - r0) : RB);
+    for (int i = j; i < RB * IN; i += BLK) {
+        const int r = i / IN;
+        xs[i] = r < nr ? x[(r0 + r) * IN + (i % IN)] : 0.0f;
+    }
+    __syncthreads();
+    float acc[RB];
+    const float b1 = p[OFF_B1 + j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = b1;
+    rows_times_column<IN>(xs, w1t, j, acc);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const float h = fmaxf(acc[r], 0.0f);
+        hs[r * HID + j] = h;
+        if (h1_out && r < nr) h1_out[(r0 + r) * HID + j] = h;
+    }
+    __syncthreads();
+    const float b2 = p[OFF_B2 + j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = b2;
+    rows_times_column<HID>(hs, w2t, j, acc);
+    const float wj = from_bf16(w3[j]);
+    const int lane = j & 63, wave = j >> 6;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+        const float h = fmaxf(acc[r], 0.0f);
+        if (h2_out && r < nr) h2_out[(r0 + r) * HID + j] = h;
+        // sum over the 64 units of the wave, in a fixed butterfly order
+        float v = h * wj;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) red[wave][r] = v;
+    }
+    __syncthreads();
+    if (j < nr) z_out[r0 + j] = ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) + p[OFF_B3];
+}
+
+// ------------------------------------------------------------ backward --
+
+// Per RB rows: dz = (sigmoid(z) - y) / B; da2 = dz w3 [h2 > 0];
+// da1 = (da2 W2) [h1 > 0].
+__global__ __launch_bounds__(BLK) void backward_act_kernel(
+    const float* __restrict__ z, const float* __restrict__ y, int64_t B,
+    const float* __restrict__ h1, const float* __restrict__ h2, const bf16_t* __restrict__ w2,
+    const bf16_t* __restrict__ w3, float* __restrict__ dz_out, float* __restrict__ da2_out,
+    float* __restrict__ da1_out)
+{
+    __shared__ __align__(16) float d2[RB * HID];
+    __shared__ float dzs[RB];
+    const int j = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * RB;
+    const int nr = (int)((B - r0) < RB ? (B - r0) : RB);
+    if (j < RB) {
+        float d = 0.0f;
+        if (j < nr) {
+            const float zz = z[r0 + j];
+            d = (1.0f / (1.0f + expf(-zz)) - y[r0 + j]) / (float)B;
+            dz_out[r0 + j] = d;
+        }
+        dzs[j] = d;
+    }
+    __syncthreads();
+    const float wj = from_bf16(w3[j]);
+    for (int r = 0; r < RB; ++r) {
+        float d = 0.0f;
+        if (r < nr && h2[(r0 + r) * HID + j] > 0.0f) d = dzs[r] * wj;
+        d2[r * HID + j] = d;
+        if (r < nr) da2_out[(r0 + r) * HID + j] = d;
+    }
+    __syncthreads();
+    // thread k: sum_j da2[r][j] W2[j][k]
+    const int k = j;
+    float acc[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[r] = 0.0f;
+    for (int jj = 0; jj < HID; jj += 4) {
+        const float w0 = from_bf16(w2[(jj + 0) * HID + k]);
+        const float w1 = from_bf16(w2[(jj + 1) * HID + k]);
+        const float w2v = from_bf16(w2[(jj + 2) * HID + k]);
+        const float w3v = from_bf16(w2[(jj + 3) * HID + k]);
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const float4 d = *reinterpret_cast<const float4*>(d2 + r * HID + jj);
+            acc[r] = fmaf(d.x, w0, fmaf(d.y, w1, fmaf(d.z, w2v, fmaf(d.w, w3v, acc[r]))));
+        }
+    }
+    for (int r = 0; r < nr; ++r) {
+        const float a = h1[(r0 + r) * HID + k] > 0.0f ? acc[r] : 0.0f;
+        da1_out[(r0 + r) * HID + k] = a;
+    }
+}
+
+// One thread per parameter; sums over the batch rows in row order, in FP64.
+__global__ void weight_grad_kernel(const float* __restrict__ x, const float* __restrict__ h1,
+                                   const float* __restrict__ h2, const float* __restrict__ dz,
+                                   const float* __restrict__ da1, const float* __restrict__ da2,
+                                   int64_t B, float* __restrict__ grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NP) return;
+    double s = 0.0;
+    if (i < OFF_B1) {
+        const int j = i / IN, k = i % IN;
+        for (int64_t r = 0; r < B; ++r) s += (double)da1[r * HID + j] * (double)x[r * IN + k];
+    } else if (i < OFF_W2) {
+        const int j = i - OFF_B1;
+        for (int64_t r = 0; r < B; ++r) s += (double)da1[r * HID + j];
+    } else if (i < OFF_B2) {
+        const int q = i - OFF_W2, j = q / HID, k = q % HID;
+        for (int64_t r = 0; r < B; ++r) s += (double)da2[r * HID + j] * (double)h1[r * HID + k];
+    } else if (i < OFF_W3) {
+        const int j = i - OFF_B2;
+        for (int64_t r = 0; r < B; ++r) s += (double)da2[r * HID + j];
+    } else if (i < OFF_B3) {
+        const int j = i - OFF_W3;
+        for (int64_t r = 0; r < B; ++r) s += (double)dz[r] * (double)h2[r * HID + j];
+    } else {
+        for (int64_t r = 0; r < B; ++r) s += (double)dz[r];
+    }
+    grad[i] = (float)s;
+}
+
+// Mean of softplus(z) - y z over the batch, one workgroup, fixed order.
+__global__ __launch_bounds__(BLK) void loss_kernel(const float* __restrict__ z,
+                                                   const float* __restrict__ y, int64_t B,
+                                                   float* __restrict__ loss)
+{
+    __shared__ double part[BLK];
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < B; r += BLK) {
+        const double zz = z[r];
+        const double sp = zz > 0.0 ? zz + log1p(exp(-zz)) : log1p(exp(zz));
+        s += sp - (double)y[r] * zz;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(part[0] / (double)B);
+}
+
+__global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                            const float* __restrict__ g, float lr, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NP) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+}
+
+// ------------------------------------------------------------- features --
+
+// One workgroup per (mc, sb) region; 64 threads build its 8 x 8 patch.
+__global__ void region_features_kernel(const float* __restrict__ stat,
+                                       const int32_t* __restrict__ n_used, int n_mc, int n_sub,
+                                       int K, double norm, float* __restrict__ out)
+{
+    const int region = blockIdx.x;
+    const int mc = region / n_sub, sb = region % n_sub;
+    __shared__ int kstar;
+    if (threadIdx.x == 0) {
+        const float* s = stat + (int64_t)region * K;
+        int best = 0;
+        float bv = s[0];
+        for (int k = 1; k < K; ++k)
+            if (s[k] > bv) {
+                bv = s[k];
+                best = k;
+            }
+        kstar = best;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= 64) return;
+    const int i = t >> 3, c = t & 7;
+    int m2 = mc - 3 + i;
+    m2 = m2 < 0 ? 0 : (m2 >= n_mc ? n_mc - 1 : m2);
+    int k = kstar - 3 + c;
+    k = k < 0 ? 0 : (k >= K ? K - 1 : k);
+    const int tm = m2 * n_sub + sb;
+    const double N = (double)n_used[tm];
+    float z = 0.0f;
+    if (N > 0.0) z = (float)(((double)stat[(int64_t)tm * K + k] * norm - N) / sqrt(N));
+    out[(int64_t)region * 64 + t] = z;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- state --
+
+struct nr_mlp_s {
+    std::string err;
+    hipStream_t stream = nullptr;
+    int64_t max_batch = 0;
+    int64_t step = 0;
+    float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    bf16_t *w1t = nullptr, *w2 = nullptr, *w2t = nullptr, *w3 = nullptr;
+    float *h1 = nullptr, *h2 = nullptr, *z = nullptr, *dz = nullptr, *da1 = nullptr, *da2 = nullptr;
+    float* loss = nullptr;
+    ~nr_mlp_s()
+    {
+        for (void* q : {(void*)p, (void*)m, (void*)v, (void*)grad, (void*)w1t, (void*)w2, (void*)w2t,
+                        (void*)w3, (void*)h1, (void*)h2, (void*)z, (void*)dz, (void*)da1, (void*)da2,
+                        (void*)loss})
+            if (q) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+bool set_err(nr_mlp m, const std::string& s)
+{
+    if (m)
+        m->err = s;
+    else
+        g_mlp_error = s;
+    return false;
+}
+
+nr_status hip_status(nr_mlp m, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return NR_OK;
+    set_err(m, std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? NR_ERR_OUT_OF_MEMORY : NR_ERR_DEVICE;
+}
+
+template <typename T>
+hipError_t dalloc(T** ptr, size_t count)
+{
+    return hipMalloc((void**)ptr, count * sizeof(T));
+}
+
+nr_status refresh(nr_mlp m)
+{
+    refresh_bf16_kernel<<<(HID * HID + 255) / 256, 256, 0, m->stream>>>(m->p, m->w1t, m->w2, m->w2t, m->w3);
+    return hip_status(m, hipGetLastError(), "weight copies");
+}
+
+nr_status check_batch(nr_mlp m, int64_t B)
+{
+    if (B < 1 || B > m->max_batch) {
+        set_err(m, "batch size " + std::to_string(B) + " outside [1, " + std::to_string(m->max_batch) + "]");
+        return NR_ERR_INVALID_ARG;
+    }
+    return NR_OK;
+}
+
+nr_status run_forward(nr_mlp m, const float* x, int64_t B, bool keep, float* logits)
+{
+    const unsigned blocks = (unsigned)((B + RB - 1) / RB);
+    forward_kernel<<<blocks, BLK, 0, m->stream>>>(x, B, m->p, m->w1t, m->w2t, m->w3, keep ? m->h1 : nullptr,
+                                                  keep ? m->h2 : nullptr, logits);
+    return hip_status(m, hipGetLastError(), "forward");
+}
+
+nr_status run_gradient(nr_mlp m, const float* x, const float* y, int64_t B, float* grad, float* loss)
+{
+    nr_status st = run_forward(m, x, B, true, m->z);
+    if (st != NR_OK) return st;
+    const unsigned blocks = (unsigned)((B + RB - 1) / RB);
+    backward_act_kernel<<<blocks, BLK, 0, m->stream>>>(m->z, y, B, m->h1, m->h2, m->w2, m->w3, m->dz, m->da2,
+                                                       m->da1);
+    if ((st = hip_status(m, hipGetLastError(), "backward")) != NR_OK) return st;
+    weight_grad_kernel<<<(NP + 255) / 256, 256, 0, m->stream>>>(x, m->h1, m->h2, m->dz, m->da1, m->da2, B, grad);
+    if ((st = hip_status(m, hipGetLastError(), "weight gradients")) != NR_OK) return st;
+    if (loss) {
+        loss_kernel<<<1, BLK, 0, m->stream>>>(m->z, y, B, loss);
+        if ((st = hip_status(m, hipGetLastError(), "loss")) != NR_OK) return st;
+    }
+    return NR_OK;
+}
+
+nr_status run_adam(nr_mlp m, const float* grad, float lr)
+{
+    m->step += 1;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)m->step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)m->step));
+    adam_kernel<<<(NP + 255) / 256, 256, 0, m->stream>>>(m->p, m->m, m->v, grad, lr, c1, c2);
+    nr_status st = hip_status(m, hipGetLastError(), "adam");
+    if (st != NR_OK) return st;
+    return refresh(m);
+}
+
+}  // namespace
+
+extern "C" {
+
+nr_status nr_mlp_create(nr_mlp* out, int64_t max_batch, void* stream)
+{
+    if (!out) {
+        g_mlp_error = "out is NULL";
+        return NR_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > (int64_t(1) << 26)) {
+        g_mlp_error = "max_batch must be in [1, 2^26]";
+        return NR_ERR_INVALID_ARG;
+    }
+    nr_mlp m = new (std::nothrow) nr_mlp_s();
+    if (!m) {
+        g_mlp_error = "host allocation failed";
+        return NR_ERR_OUT_OF_MEMORY;
+    }
+    m->stream = (hipStream_t)stream;
+    m->max_batch = max_batch;
+    hipError_t e = hipSuccess;
+    const size_t act = (size_t)max_batch * HID;
+    if (e == hipSuccess) e = dalloc(&m->p, NP);
+    if (e == hipSuccess) e = dalloc(&m->m, NP);
+    if (e == hipSuccess) e = dalloc(&m->v, NP);
+    if (e == hipSuccess) e = dalloc(&m->grad, NP);
+    if (e == hipSuccess) e = dalloc(&m->w1t, (size_t)HID * IN);
+    if (e == hipSuccess) e = dalloc(&m->w2, (size_t)HID * HID);
+    if (e == hipSuccess) e = dalloc(&m->w2t, (size_t)HID * HID);
+    if (e == hipSuccess) e = dalloc(&m->w3, (size_t)HID);
+    if (e == hipSuccess) e = dalloc(&m->h1, act);
+    if (e == hipSuccess) e = dalloc(&m->h2, act);
+    if (e == hipSuccess) e = dalloc(&m->da1, act);
+    if (e == hipSuccess) e = dalloc(&m->da2, act);
+    if (e == hipSuccess) e = dalloc(&m->z, (size_t)max_batch);
+    if (e == hipSuccess) e = dalloc(&m->dz, (size_t)max_batch);
+    if (e == hipSuccess) e = dalloc(&m->loss, 1);
+    if (e == hipSuccess) e = hipMemsetAsync(m->p, 0, NP * sizeof(float), m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, NP * sizeof(float), m->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, NP * sizeof(float), m->stream);
+    if (e != hipSuccess) {
+        g_mlp_error = std::string("device allocation failed: ") + hipGetErrorString(e);
+        delete m;
+        return NR_ERR_OUT_OF_MEMORY;
+    }
+    if (refresh(m) != NR_OK) {
+        g_mlp_error = m->err;
+        delete m;
+        return NR_ERR_DEVICE;
+    }
+    *out = m;
+    return NR_OK;
+}
+
+nr_status nr_mlp_set_params(nr_mlp m, const float* host_params)
+{
+    if (!m || !host_params) return NR_ERR_INVALID_ARG;
+    nr_status st = hip_status(m, hipMemcpyAsync(m->p, host_params, NP * sizeof(float), hipMemcpyHostToDevice, m->stream),
+                              "parameter upload");
+    if (st == NR_OK) st = hip_status(m, hipMemsetAsync(m->m, 0, NP * sizeof(float), m->stream), "moments");
+    if (st == NR_OK) st = hip_status(m, hipMemsetAsync(m->v, 0, NP * sizeof(float), m->stream), "moments");
+    if (st == NR_OK) st = refresh(m);
+    if (st == NR_OK) st = hip_status(m, hipStreamSynchronize(m->stream), "parameter upload");
+    m->step = 0;
+    return st;
+}
+
+nr_status nr_mlp_get_params(nr_mlp m, float* host_params)
+{
+    if (!m || !host_params) return NR_ERR_INVALID_ARG;
+    nr_status st = hip_status(m, hipMemcpyAsync(host_params, m->p, NP * sizeof(float), hipMemcpyDeviceToHost, m->stream),
+                              "parameter download");
+    if (st == NR_OK) st = hip_status(m, hipStreamSynchronize(m->stream), "parameter download");
+    return st;
+}
+
+nr_status nr_mlp_forward(nr_mlp m, const float* x, int64_t B, float* logits)
+{
+    if (!m || !x || !logits) return NR_ERR_INVALID_ARG;
+    if (B < 1) {
+        set_err(m, "batch size must be >= 1");
+        return NR_ERR_INVALID_ARG;
+    }
+    // inference keeps no activations, so any batch size streams through
+    return run_forward(m, x, B, false, logits);
+}
+
+nr_status nr_mlp_gradient(nr_mlp m, const float* x, const float* y, int64_t B, float* grad, float* loss)
+{
+    if (!m || !x || !y) return NR_ERR_INVALID_ARG;
+    nr_status st = check_batch(m, B);
+    if (st != NR_OK) return st;
+    st = run_gradient(m, x, y, B, m->grad, loss);
+    if (st == NR_OK && grad)
+        st = hip_status(m, hipMemcpyAsync(grad, m->grad, NP * sizeof(float), hipMemcpyDeviceToDevice, m->stream),
+                        "gradient copy");
+    return st;
+}
+
+nr_status nr_mlp_adam_step(nr_mlp m, const float* grad, float lr)
+{
+    if (!m || !grad || !(lr > 0.0f)) return NR_ERR_INVALID_ARG;
+    return run_adam(m, grad, lr);
+}
+
+nr_status nr_mlp_train_step(nr_mlp m, const float* x, const float* y, int64_t B, float lr, float* loss)
+{
+    if (!m || !x || !y || !(lr > 0.0f)) return NR_ERR_INVALID_ARG;
+    nr_status st = check_batch(m, B);
+    if (st != NR_OK) return st;
+    st = run_gradient(m, x, y, B, m->grad, loss);
+    if (st != NR_OK) return st;
+    return run_adam(m, m->grad, lr);
+}
+
+nr_status nr_mlp_region_features(const float* stat, const int32_t* n_used, int32_t n_mc, int32_t n_sub,
+                                 int32_t K, double norm, float* features, void* stream)
+{
+    if (!stat || !n_used || !features || n_mc < 1 || n_sub < 1 || K < 1 || K > 4096 || !(norm > 0.0)) {
+        g_mlp_error = "invalid region feature arguments";
+        return NR_ERR_INVALID_ARG;
+    }
+    region_features_kernel<<<(unsigned)((int64_t)n_mc * n_sub), 64, 0, (hipStream_t)stream>>>(
+        stat, n_used, n_mc, n_sub, K, norm, features);
+    return hip_status(nullptr, hipGetLastError(), "region features");
+}
+
+const char* nr_mlp_last_error(nr_mlp m) { return m ? m->err.c_str() : g_mlp_error.c_str(); }
+
+void nr_mlp_destroy(nr_mlp m)
+{
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    delete m;
+}
+
+}  // extern "C"

@@ -1,16 +1,16 @@
 // Host-side NUFFT and resampling parameters (no device code).
 #pragma once
 
+#include <cstddef>
 #include <vector>
 
 namespace nr {
 
 constexpr double kFp32MinTol = 1e-6;   // FP32 spreading/FFT reach about 1e-6 relative l2
 constexpr double kFp64MinTol = 1e-12;  // below this the kernel width table ends
-// Largest upsampled grid: four per-wave grid copies of the spreader share one
-// workgroup's LDS (160 KiB on gfx950).
-constexpr int kMaxGridF32 = 5120;
-constexpr int kMaxGridF64 = 2560;
+// LDS of one gfx950 workgroup; the spreader's four per-wave grid copies and
+// its phase table must fit, which bounds the upsampled grid size.
+constexpr size_t kLdsBytes = 160 * 1024;
 
 // beta(f0, Mc) of Eq. (beta) in s^-1 (0 for Mc = 0).
 double chirp_beta(double mc_msun, double f0);

@@ -86,7 +86,8 @@ struct Class {
     std::vector<int32_t> tmpl_id, tmpl_list;
     std::vector<int64_t> tmpl_list_off, tmpl_stat_off;
     // device copies
-    DevBuf d_inst, d_coef, d_taps, d_dec, d_tw, d_segs, d_strain, d_tmpl_id, d_tmpl_list,
+    int flush_period = 16;
+    DevBuf d_inst, d_coef, d_taps, d_dec, d_tw, d_phase, d_segs, d_strain, d_tmpl_id, d_tmpl_list,
         d_tmpl_list_off, d_tmpl_stat_off;
 };
 
@@ -110,6 +111,21 @@ struct nr_plan_s {
     int64_t n_invalid = 0;
     int64_t workspace = 0;
     int n_chunks = 0;
+    // profiling: (stage, start, end) events of launches not yet read
+    struct Timed {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    ~nr_plan_s()
+    {
+        for (auto& t : timed) {
+            (void)hipEventDestroy(t.a);
+            (void)hipEventDestroy(t.b);
+        }
+        for (auto e : event_pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -172,11 +188,12 @@ struct InstHost {
     double y_max;
 };
 
-// Validity rule and tau constants of one instance (long double host math).
-InstHost instance_constants(const nr_segment& g, const nr_template& t)
+// Validity rule and tau constants of one instance (long double host math);
+// beta is the template's Eq. (beta) value.
+InstHost instance_constants(const nr_segment& g, const nr_template& t, double beta)
 {
     InstHost h{};
-    h.beta = chirp_beta(t.mc_msun, t.f0);
+    h.beta = beta;
     if (h.beta == 0.0) {
         h.valid = true;
         h.c = 1.0L / (long double)g.fs;
@@ -201,6 +218,19 @@ InstHost instance_constants(const nr_segment& g, const nr_template& t)
 // Horner coefficients b_k (k = 1..d) of dtau(j) = a sum_k e_k (c j)^k, the
 // binomial series of 1 - (1 - y)^{5/8}; returns d, or -1 when the series
 // needs more than kMaxHorner terms for the requested phase accuracy.
+// e_k of 1 - (1 - y)^{5/8} = sum_k e_k y^k (all positive): e_1 = 5/8,
+// e_k = e_{k-1} (k - 1 - 5/8) / k.
+const std::vector<long double>& binomial_e()
+{
+    static const std::vector<long double> e = [] {
+        std::vector<long double> v(kMaxHorner + 2, 0.0L);
+        v[1] = 0.625L;
+        for (int k = 2; k <= kMaxHorner + 1; ++k) v[k] = v[k - 1] * ((long double)(k - 1) - 0.625L) / (long double)k;
+        return v;
+    }();
+    return e;
+}
+
 int horner_series(const InstHost& h, double f_ref, double cyc_tol, std::vector<double>& out)
 {
     const long double y = h.y_max;
@@ -209,17 +239,17 @@ int horner_series(const InstHost& h, double f_ref, double cyc_tol, std::vector<d
         return 1;
     }
     if (y >= 0.9L) return -1;
-    std::vector<long double> e(kMaxHorner + 2);
-    e[1] = 0.625L;
-    for (int k = 2; k <= kMaxHorner + 1; ++k) e[k] = e[k - 1] * ((long double)(k - 1) - 0.625L) / (long double)k;
+    const std::vector<long double>& e = binomial_e();
     int d = -1;
+    long double yk1 = y * y;  // y^{k+1}
+    const long double scale = h.a * (long double)f_ref / (1.0L - y);
     for (int k = 1; k <= kMaxHorner; ++k) {
         // terms are positive and fall at least geometrically with ratio y
-        const long double tail = h.a * e[k + 1] * powl(y, (long double)(k + 1)) / (1.0L - y);
-        if (tail * (long double)f_ref <= (long double)cyc_tol) {
+        if (scale * e[k + 1] * yk1 <= (long double)cyc_tol) {
             d = k;
             break;
         }
+        yk1 *= y;
     }
     if (d < 0) return -1;
     long double ck = 1.0L;
@@ -271,14 +301,24 @@ void build_class_tables(Class& c, double tol_cls, double sigma)
         tw[2 * t + 1] = sinl(ang);
     }
     c.radix = fft_radices(c.n);
+    // coarse heterodyne phasors exp(2 pi i k / N)
+    const int NT = phase_table_size(c.fp64);
+    std::vector<long double> ph(2 * (size_t)NT);
+    for (int k = 0; k < NT; ++k) {
+        const long double ang = 2.0L * 3.14159265358979323846264338327950288L * k / NT;
+        ph[2 * k] = cosl(ang);
+        ph[2 * k + 1] = sinl(ang);
+    }
     if (c.fp64) {
         c.d_taps.upload(cast_vec<double>(taps), "kernel pieces");
         c.d_dec.upload(cast_vec<double>(dec), "deconvolution");
         c.d_tw.upload(cast_vec<double>(tw), "twiddles");
+        c.d_phase.upload(cast_vec<double>(ph), "phase table");
     } else {
         c.d_taps.upload(cast_vec<float>(taps), "kernel pieces");
         c.d_dec.upload(cast_vec<float>(dec), "deconvolution");
         c.d_tw.upload(cast_vec<float>(tw), "twiddles");
+        c.d_phase.upload(cast_vec<float>(ph), "phase table");
     }
     (void)sigma;
 }
@@ -335,12 +375,26 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
 
     std::map<ClassKey, size_t> class_of;
     std::map<ClassKey, double> class_tol;
-    std::vector<std::vector<int64_t>> members;
-    std::vector<std::vector<double>> coefs;
+    // largest grid whose spreader LDS (grids plus phase table) fits a workgroup
+    int n_max_of[2];
+    for (int f = 0; f < 2; ++f) {
+        int lo = 1, hi = 1 << 16;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (spread_lds_bytes(f, mid) <= kLdsBytes) lo = mid; else hi = mid - 1;
+        }
+        n_max_of[f] = lo;
+    }
+    std::vector<double> tmpl_beta(n_tmpls);
+    for (int32_t m = 0; m < n_tmpls; ++m) tmpl_beta[m] = chirp_beta(P.tmpls[m].mc_msun, P.tmpls[m].f0);
+    // kernel width per distinct tolerance, and the last class looked up
+    std::map<std::pair<double, int>, int> width_of;
+    ClassKey last_key{-1, -1, -1, -1};
+    size_t last_ci = 0;
     for (int64_t i = 0; i < N; ++i) {
         const nr_segment& g = P.segs[P.inst_seg[i]];
         const nr_template& t = P.tmpls[P.inst_tmpl[i]];
-        const InstHost h = instance_constants(g, t);
+        const InstHost h = instance_constants(g, t, tmpl_beta[P.inst_tmpl[i]]);
         if (!h.valid) continue;
         P.valid[i] = 1;
         ++P.n_valid;
@@ -350,17 +404,30 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         const double tol_eff = std::max(inst_tol[i], fp64 ? kFp64MinTol : kFp32MinTol);
         const int w = kernel_width(tol_eff, sigma);
         const int K = t.n_bins;
-        const int n = fft_size(std::max((int64_t)std::ceil(sigma * K - 1e-9), (int64_t)2 * w));
-        const int n_max = fp64 ? kMaxGridF64 : kMaxGridF32;
+        int n;
+        {
+            auto wk = width_of.find({sigma * K, w});
+            if (wk == width_of.end()) {
+                n = fft_size(std::max((int64_t)std::ceil(sigma * K - 1e-9), (int64_t)2 * w));
+                width_of[{sigma * K, w}] = n;
+            } else {
+                n = wk->second;
+            }
+        }
+        const int n_max = n_max_of[fp64];
         if (n > n_max)
             fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": grid size " + std::to_string(n) +
                                          " exceeds the supported maximum " + std::to_string(n_max) +
                                          " (lower n_bins or sigma)");
         const int parts = o.parts ? o.parts : default_parts(g.n_samples);
         ClassKey key{fp64, w, n, parts};
-        auto it = class_of.find(key);
         size_t ci;
-        if (it == class_of.end()) {
+        const bool same = !(key < last_key) && !(last_key < key);
+        auto it = same ? class_of.end() : class_of.find(key);
+        if (same) {
+            ci = last_ci;
+            if (tol_eff < class_tol[key]) class_tol[key] = tol_eff;
+        } else if (it == class_of.end()) {
             ci = P.classes.size();
             class_of[key] = ci;
             class_tol[key] = tol_eff;
@@ -371,11 +438,12 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             c->parts = parts;
             c->beta_es = es_beta(w, sigma);
             P.classes.push_back(std::move(c));
-            members.emplace_back();
         } else {
             ci = it->second;
             class_tol[key] = std::min(class_tol[key], tol_eff);
         }
+        last_key = key;
+        last_ci = ci;
         Class& c = *P.classes[ci];
         InstDev d{};
         const double df = t.df > 0.0 ? t.df : g.fs / (double)g.n_samples;
@@ -410,15 +478,14 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     int64_t fixed_bytes = 0;
     for (auto& cp : P.classes) {
         Class& c = *cp;
-        std::map<int32_t, int64_t> seg_at;
+        std::vector<int64_t> seg_at(P.n_segs, -1);
         const int esize = (c.fp64 ? 8 : 4) * (o.strain_complex ? 2 : 1);
         int64_t pt = 0;
-        std::map<int32_t, int32_t> tmpl_at;
+        std::vector<int32_t> tmpl_at(P.n_tmpls, -1);
         std::vector<std::vector<int32_t>> lists;
         for (size_t k = 0; k < c.inst.size(); ++k) {
             InstDev& d = c.inst[k];
-            auto it = seg_at.find(d.seg);
-            if (it == seg_at.end()) {
+            if (seg_at[d.seg] < 0) {
                 SegDev sd{};
                 sd.src_off = P.segs[d.seg].sample_offset;
                 sd.dst_off = c.strain_entries;
@@ -427,29 +494,36 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
                 c.segs.push_back(sd);
                 seg_at[d.seg] = sd.dst_off;
                 c.strain_entries += (int64_t)c.parts * d.C * kWave;
-                d.strain_off = sd.dst_off;
-            } else {
-                d.strain_off = it->second;
             }
+            d.strain_off = seg_at[d.seg];
             d.pt_off = pt;
             pt += (int64_t)c.parts * d.C * kWave;
             d.bin_off = P.bin_off[d.inst];
             const int32_t pm = P.inst_tmpl[d.inst];
-            auto jt = tmpl_at.find(pm);
-            if (jt == tmpl_at.end()) {
+            if (tmpl_at[pm] < 0) {
                 tmpl_at[pm] = (int32_t)c.tmpl_id.size();
                 c.tmpl_id.push_back(pm);
                 c.tmpl_stat_off.push_back(P.stat_off[pm]);
                 lists.emplace_back();
-                lists.back().push_back((int32_t)k);
-            } else {
-                lists[jt->second].push_back((int32_t)k);
             }
+            lists[tmpl_at[pm]].push_back((int32_t)k);
         }
         c.tmpl_list_off.push_back(0);
         for (auto& l : lists) {
             c.tmpl_list.insert(c.tmpl_list.end(), l.begin(), l.end());
             c.tmpl_list_off.push_back((int64_t)c.tmpl_list.size());
+        }
+        // collective flush period: about half the samples a lane spends in one cell
+        {
+            long double pts_per_cell = 0.0L;
+            for (const InstDev& d : c.inst) {
+                const long double span = std::max(1.0L, (long double)d.df * d.L / (long double)P.segs[d.seg].fs);
+                pts_per_cell += (long double)d.L / ((long double)c.n * span);
+            }
+            pts_per_cell /= std::max<size_t>(c.inst.size(), 1);
+            int f = 1;
+            while (f < 64 && 2.0L * f * 2.0L <= pts_per_cell) f *= 2;
+            c.flush_period = f;
         }
         // class template of each class instance, to bound each chunk's template range
         std::vector<int32_t> ct_of(c.inst.size());
@@ -482,7 +556,8 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         P.n_chunks += (int)c.chunks.size();
         // device tables
         c.d_inst.upload(c.inst, "instances");
-        c.d_coef.upload(c.coef.empty() ? std::vector<double>{0.0} : c.coef, "tau series");
+        c.coef.resize(c.coef.size() + kHornerPad, 0.0);  // whole-width register loads stay in bounds
+        c.d_coef.upload(c.coef, "tau series");
         c.d_segs.upload(c.segs, "segments");
         c.d_strain.alloc((size_t)c.strain_entries * esize, "lane-major strain");
         c.d_tmpl_id.upload(c.tmpl_id, "templates");
@@ -490,7 +565,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         c.d_tmpl_list_off.upload(c.tmpl_list_off, "template lists");
         c.d_tmpl_stat_off.upload(c.tmpl_stat_off, "template offsets");
         P.workspace += (int64_t)(c.d_inst.bytes + c.d_coef.bytes + c.d_segs.bytes + c.d_strain.bytes +
-                                 c.d_taps.bytes + c.d_dec.bytes + c.d_tw.bytes + c.d_tmpl_id.bytes +
+                                 c.d_phase.bytes + c.d_taps.bytes + c.d_dec.bytes + c.d_tw.bytes + c.d_tmpl_id.bytes +
                                  c.d_tmpl_list.bytes + c.d_tmpl_list_off.bytes + c.d_tmpl_stat_off.bytes);
     }
     if (fixed_bytes + grid_chunk_bytes + point_chunk_bytes > cap)
@@ -513,6 +588,33 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
 
 // ------------------------------------------------------------ execution --
 
+hipEvent_t take_event(nr_plan_s& P)
+{
+    if (!P.event_pool.empty()) {
+        hipEvent_t e = P.event_pool.back();
+        P.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hip_check(hipEventCreate(&e), "event create");
+    return e;
+}
+
+// Launch through f, bracketed by events when the plan profiles.
+template <typename F>
+void timed_launch(nr_plan_s& P, int stage, F&& f, const char* what)
+{
+    if (!P.opt.profile) {
+        hip_check(f(), what);
+        return;
+    }
+    hipEvent_t a = take_event(P), b = take_event(P);
+    hip_check(hipEventRecord(a, P.stream), "event record");
+    hip_check(f(), what);
+    hip_check(hipEventRecord(b, P.stream), "event record");
+    P.timed.push_back({stage, a, b});
+}
+
 SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
 {
     SpreadArgs a{};
@@ -520,6 +622,7 @@ SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     a.coef = (const double*)c.d_coef.p;
     a.taps = c.d_taps.p;
     a.strain_lm = c.d_strain.p;
+    a.phase_table = c.d_phase.p;
     a.points = P.d_points.p;
     a.grid = P.d_grid.p;
     a.first = ch.first;
@@ -528,7 +631,7 @@ SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     a.n = c.n;
     a.w = c.w;
     a.parts = c.parts;
-    a.flush_period = 16;
+    a.flush_period = c.flush_period;
     a.strain_complex = P.opt.strain_complex;
     return a;
 }
@@ -571,15 +674,19 @@ void check_finite(nr_plan_s& P, const void* strain)
 void run_front(nr_plan_s& P, Class& c, const Chunk& ch)
 {
     SpreadArgs a = spread_args(P, c, ch);
-    if (P.method == NR_METHOD_STAGED) hip_check(launch_tau(a, c.fp64, P.stream), "tau kernel");
-    hip_check(launch_spread(a, c.fp64, c.deg, P.method == NR_METHOD_FUSED, P.stream), "spread kernel");
+    if (P.method == NR_METHOD_STAGED)
+        timed_launch(P, NR_STAGE_TAU, [&] { return launch_tau(a, c.fp64, P.stream); }, "tau kernel");
+    timed_launch(P, NR_STAGE_SPREAD,
+                 [&] { return launch_spread(a, c.fp64, c.deg, P.method == NR_METHOD_FUSED, P.stream); },
+                 "spread kernel");
 }
 
 void lane_major(nr_plan_s& P, Class& c, const void* strain)
 {
-    hip_check(launch_strain_lane_major((const SegDev*)c.d_segs.p, (int32_t)c.segs.size(), c.parts, strain,
-                                       P.strain_fp64, P.opt.strain_complex, c.d_strain.p, c.fp64, P.stream),
-              "strain layout");
+    timed_launch(P, NR_STAGE_LAYOUT, [&] {
+        return launch_strain_lane_major((const SegDev*)c.d_segs.p, (int32_t)c.segs.size(), c.parts, strain,
+                                        P.strain_fp64, P.opt.strain_complex, c.d_strain.p, c.fp64, P.stream);
+    }, "strain layout");
 }
 
 void execute(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid)
@@ -595,15 +702,17 @@ void execute(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8
             e.spectra = spectra;
             e.power = power;
             if (spectra || power)
-                hip_check(launch_epilogue_spectra(e, c.fp64, P.out_fp64, P.stream), "epilogue");
+                timed_launch(P, NR_STAGE_EPILOGUE,
+                             [&] { return launch_epilogue_spectra(e, c.fp64, P.out_fp64, P.stream); }, "epilogue");
         }
     }
     if (spectra || power || valid)
-        hip_check(launch_fill_invalid((const int32_t*)P.d_invalid.p, (const int64_t*)P.d_bin_off.p,
-                                      (const int32_t*)P.d_inst_K.p, (spectra || power) ? P.n_invalid : 0,
-                                      spectra, power, P.out_fp64, (const uint8_t*)P.d_mask.p, valid,
-                                      P.n_inst, P.stream),
-                  "invalid fill");
+        timed_launch(P, NR_STAGE_EPILOGUE, [&] {
+            return launch_fill_invalid((const int32_t*)P.d_invalid.p, (const int64_t*)P.d_bin_off.p,
+                                       (const int32_t*)P.d_inst_K.p, (spectra || power) ? P.n_invalid : 0,
+                                       spectra, power, P.out_fp64, (const uint8_t*)P.d_mask.p, valid,
+                                       P.n_inst, P.stream);
+        }, "invalid fill");
 }
 
 void semicoherent(nr_plan_s& P, const void* strain, const double* w, void* stat, int32_t* n_used)
@@ -619,7 +728,8 @@ void semicoherent(nr_plan_s& P, const void* strain, const double* w, void* stat,
             e.seg_weight = w;
             e.stat = stat;
             e.n_used = n_used;
-            hip_check(launch_epilogue_sum(e, c.fp64, P.out_fp64, P.stream), "segment sum");
+            timed_launch(P, NR_STAGE_EPILOGUE,
+                         [&] { return launch_epilogue_sum(e, c.fp64, P.out_fp64, P.stream); }, "segment sum");
         }
     }
 }
@@ -700,6 +810,24 @@ nr_status nufft_resample_semicoherent_sum(nr_plan p, const void* strain, const d
     return guarded(p, [&] { semicoherent(*p, strain, seg_weight, stat, n_used); });
 }
 
+nr_status nufft_resample_stage_times(nr_plan p, nr_stage_times* out)
+{
+    if (!p || !out) return NR_ERR_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    return guarded(p, [&] {
+        for (auto& t : p->timed) {
+            hip_check(hipEventSynchronize(t.b), "event sync");
+            float ms = 0.0f;
+            hip_check(hipEventElapsedTime(&ms, t.a, t.b), "event time");
+            out->ms[t.stage] += ms;
+            out->launches[t.stage] += 1;
+            p->event_pool.push_back(t.a);
+            p->event_pool.push_back(t.b);
+        }
+        p->timed.clear();
+    });
+}
+
 nr_status nufft_resample_query(nr_plan p, nr_plan_info* info)
 {
     if (!p || !info) return NR_ERR_INVALID_ARG;
@@ -735,6 +863,10 @@ nr_status nufft_resample_query_class(nr_plan p, int32_t ci, nr_class_info* info)
     info->beta_es = c.beta_es;
     info->n_inst = (int64_t)c.inst.size();
     info->n_points = c.n_points;
+    for (const InstDev& d : c.inst) {
+        if (d.ndeg > 0) info->series_terms += (int64_t)d.L * d.ndeg;
+        if (d.ndeg < 0) info->fallback_points += d.L;
+    }
     return NR_OK;
 }
 

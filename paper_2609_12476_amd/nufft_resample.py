@@ -42,7 +42,8 @@ class NrInstance(ctypes.Structure):
 class NrOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("method", c_int32), ("sigma", c_double),
                 ("strain_complex", c_int32), ("strict", c_int32), ("check_finite", c_int32),
-                ("parts", c_int32), ("strain_length", c_int64), ("max_workspace_bytes", c_int64),
+                ("parts", c_int32), ("profile", c_int32), ("reserved", c_int32),
+                ("strain_length", c_int64), ("max_workspace_bytes", c_int64),
                 ("stream", c_void_p), ("tune_cache", c_char_p)]
 
 
@@ -53,10 +54,18 @@ class NrPlanInfo(ctypes.Structure):
                 ("n_chunks", c_int32)]
 
 
+class NrStageTimes(ctypes.Structure):
+    _fields_ = [("ms", c_double * 4), ("launches", c_int64 * 4)]
+
+
+STAGES = ("layout", "tau", "spread", "epilogue")
+
+
 class NrClassInfo(ctypes.Structure):
     _fields_ = [("fp64", c_int32), ("w", c_int32), ("n", c_int32), ("degree", c_int32),
                 ("parts", c_int32), ("n_radix", c_int32), ("radix", c_int32 * 8),
-                ("beta_es", c_double), ("n_inst", c_int64), ("n_points", c_int64)]
+                ("beta_es", c_double), ("n_inst", c_int64), ("n_points", c_int64),
+                ("series_terms", c_int64), ("fallback_points", c_int64)]
 
 
 # symbol -> (restype, argtypes)
@@ -70,6 +79,7 @@ SIGNATURES = {
     "nufft_resample_semicoherent_sum": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                                   c_void_p]),
     "nufft_resample_query": (c_int32, [c_void_p, ctypes.POINTER(NrPlanInfo)]),
+    "nufft_resample_stage_times": (c_int32, [c_void_p, ctypes.POINTER(NrStageTimes)]),
     "nufft_resample_query_class": (c_int32, [c_void_p, c_int32, ctypes.POINTER(NrClassInfo)]),
     "nufft_resample_bin_offsets": (c_int32, [c_void_p, c_void_p]),
     "nufft_resample_stat_offsets": (c_int32, [c_void_p, c_void_p]),
@@ -142,6 +152,12 @@ def nufft_resample_query(plan):
     info = NrPlanInfo()
     _check(load().nufft_resample_query(plan, ctypes.byref(info)), plan)
     return info
+
+
+def nufft_resample_stage_times(plan):
+    t = NrStageTimes()
+    _check(load().nufft_resample_stage_times(plan, ctypes.byref(t)), plan)
+    return {STAGES[i]: (t.ms[i], t.launches[i]) for i in range(4)}
 
 
 def nufft_resample_query_class(plan, c):
@@ -233,7 +249,7 @@ class Plan:
 
     def __init__(self, segs, tmpls, inst=None, tol=1e-6, precision="fp32", method="auto",
                  sigma=2.0, strict=False, parts=0, strain_complex=False, strain_length=0,
-                 max_workspace_bytes=0, check_finite=False, stream=None):
+                 max_workspace_bytes=0, check_finite=False, profile=False, stream=None):
         import torch
         opt = nufft_resample_default_options()
         opt.precision = _PRECISION[precision]
@@ -245,6 +261,7 @@ class Plan:
         opt.strain_length = int(strain_length)
         opt.max_workspace_bytes = int(max_workspace_bytes)
         opt.check_finite = int(bool(check_finite))
+        opt.profile = int(bool(profile))
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -284,6 +301,10 @@ class Plan:
 
     def valid_mask(self):
         return nufft_resample_valid_mask(self.handle, self.n_inst)
+
+    def stage_times(self):
+        """{stage: (summed kernel ms, launches)} since the last read (profile plans)."""
+        return nufft_resample_stage_times(self.handle)
 
     # -- device work -------------------------------------------------------------
     def strain_tensor(self, x, device="cuda"):

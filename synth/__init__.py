@@ -295,3 +295,26 @@ def random_small(seed, L, K, mc, f0=50.0, fs=64.0, f_lo=None, df=None, t_start=0
         seg_fs=np.array([fs]), seg_t=np.array([t_start]),
         mc=np.array([mc]), f0=np.array([f0]), f_lo=np.array([f_lo]), df=np.array([df]),
         n_bins=np.array([K], np.int32), f_max=np.array([0.0]), tol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Learned-proposal inputs
+# --------------------------------------------------------------------------
+
+MLP_SHAPES = [("W1", (256, 64)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)),
+              ("w3", (256,)), ("b3", (1,))]
+
+
+def mlp_init_params(seed):
+    """He-uniform initial weights and zero biases of the 64-256-256-1 network,
+    flattened as W1[256][64], b1, W2[256][256], b2, w3[256], b3 (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in MLP_SHAPES:
+        if name.startswith("b"):
+            parts.append(np.zeros(shape))
+        else:
+            fan_in = shape[-1] if len(shape) == 2 else 256
+            lim = math.sqrt(6.0 / fan_in)
+            parts.append(rng.uniform(-lim, lim, size=shape))
+    return np.concatenate([q.ravel() for q in parts]).astype(np.float32)

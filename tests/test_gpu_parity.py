@@ -187,12 +187,14 @@ def test_small_and_ragged_sizes(gpu, L, K, mc, prec):
     assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
 
 
+@pytest.mark.parametrize("method", ["fused", "staged"])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_complex_strain(gpu, prec):
-    say(f"complex strain {prec}")
+def test_complex_strain(gpu, prec, method):
+    say(f"complex strain {prec} {method}")
     w = synth.random_small(3, 3000, 64, 2e-2, f0=45.0, fs=128.0, complex_strain=True)
     Xr, off, ok = oracle.spectra(w)
-    X, _, _, _, _ = run_plan(w, gpu, precision=prec, tol=1e-6 if prec == "fp32" else 1e-10)
+    X, _, _, _, _ = run_plan(w, gpu, precision=prec, method=method,
+                             tol=1e-6 if prec == "fp32" else 1e-10)
     assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
 
 
