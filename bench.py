@@ -54,6 +54,10 @@ def parse():
                     help="instances timed on the oracle (seeded sample)")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain copy kernel run once for counter calibration")
+    ap.add_argument("--workload", default="semicoherent_1h",
+                    choices=["semicoherent_1h", "full_sweep_6h", "ragged_512", "paper_beta_bank"],
+                    help="semicoherent_1h is the headline; the others print their own line")
+    ap.add_argument("--tune", action="store_true", help="autotune the spreader per shape")
     return ap.parse_args()
 
 
@@ -93,6 +97,77 @@ def time_steps(plan, x, stat, used, steps, warmup):
     return t1 - t0, plan.stage_times()
 
 
+def other_workload(args, dev):
+    """Throughput of the non-headline workloads (one JSON line each)."""
+    import torch
+
+    import oracle
+    import synth
+    from paper_2609_12476_amd import Plan, complex_view
+
+    stream = torch.cuda.Stream()
+    out = {"unit": "spectra/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic"}
+    with torch.cuda.stream(stream):
+        if args.workload == "ragged_512":
+            w = synth.ragged_batch(n_inst=512, seed=2)
+            kw = dict(precision="auto", use_graph=True, tune=args.tune)
+            mode = "execute"
+        elif args.workload == "paper_beta_bank":
+            w = synth.paper_bank(hours=1.0).as_float32_strain()
+            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune)
+            mode = "execute"
+        else:
+            w = synth.semicoherent(hours=6.0, n_mc=2048, n_sub=20, seed=3, tol=1e-6).as_float32_strain()
+            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune)
+            mode = "sum"
+        log(f"{w.name}: planning {w.n_inst} instances")
+        t0 = time.perf_counter()
+        plan = Plan.from_workload(w, stream=stream, **kw)
+        plan_s = time.perf_counter() - t0
+        x = plan.strain_tensor(w.strain, dev)
+        info = plan.info
+        if mode == "execute":
+            sp = torch.empty(2 * info.total_bins, dtype=plan.out_dtype, device=dev)
+            pw = torch.empty(info.total_bins, dtype=plan.out_dtype, device=dev)
+            va = torch.empty(plan.n_inst, dtype=torch.uint8, device=dev)
+            step = lambda: plan.execute(x, sp, pw, va)
+        else:
+            st = torch.zeros(info.stat_bins, dtype=plan.out_dtype, device=dev)
+            us = torch.zeros(plan.n_tmpls, dtype=torch.int32, device=dev)
+            step = lambda: plan.semicoherent_sum(x, None, st, us)
+        steps = max(2, args.steps // (10 if mode == "sum" else 1))
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        cls = plan.classes()
+        out.update({"metric": f"{w.name} spectra/s", "value": info.n_valid * steps / el,
+                    "ms_per_step": el / steps * 1e3, "steps": steps, "warmup": args.warmup,
+                    "config": {"workload": w.name, "instances": int(info.n_inst), "valid": int(info.n_valid),
+                               "classes": len(cls), "chunks": int(info.n_chunks), "graph": True,
+                               "tuned": bool(args.tune), "plan_seconds": plan_s},
+                    "class_shapes": [(c.fp64, c.w, c.n, c.degree, c.parts, c.method, c.flush_period, c.n_inst)
+                                     for c in cls]})
+        # sampled parity against the oracle
+        rng = np.random.default_rng(7)
+        ok = plan.valid_mask().astype(bool)
+        idx = np.sort(rng.choice(np.flatnonzero(ok), size=min(16, int(ok.sum())), replace=False))
+        sp2, _, _ = plan.execute(x, want=("spectra",))
+        torch.cuda.synchronize()
+        X = complex_view(sp2).cpu().numpy().astype(np.complex128)
+        Xr, off, _ = oracle.spectra(w, inst_idx=idx)
+        boff = plan.bin_offsets()
+        errs = [np.linalg.norm(X[boff[i]:boff[i + 1]] - Xr[off[j]:off[j + 1]]) /
+                np.linalg.norm(Xr[off[j]:off[j + 1]]) for j, i in enumerate(idx)]
+        out["oracle_check"] = {"instances": len(idx), "spectra_rel_l2_max": float(np.max(errs))}
+        plan.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -108,6 +183,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload != "semicoherent_1h":
+        return other_workload(args, dev)
     log("generating workload")
     w = synth.semicoherent(hours=args.hours, n_mc=args.n_mc, n_sub=20, seed=1, tol=1e-6)
     w32 = w.as_float32_strain()           # the FP32 path's input values; the FP64 runs use the same

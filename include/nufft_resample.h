@@ -118,11 +118,21 @@ typedef struct {
     int32_t check_finite;       /* 1: execute scans the strain and synchronises */
     int32_t parts;              /* waves per instance in the spreader; 0: automatic */
     int32_t profile;            /* 1: time every kernel launch with HIP events */
-    int32_t reserved;
+    int32_t use_graph;          /* 1: capture each call's launches in a HIP graph, keyed by
+                                   its pointer arguments, and replay it on later calls with
+                                   the same pointers (needs a non-null stream; ignored with
+                                   profile or check_finite) */
     int64_t strain_length;      /* samples in the strain array; 0: not checked */
     int64_t max_workspace_bytes;/* device workspace cap; 0: 8 GiB */
     void* stream;               /* hipStream_t of every enqueue; NULL: the null stream */
-    const char* tune_cache;     /* autotuner cache file; NULL: no tuning */
+    const char* tune_cache;     /* autotuner cache file read before and written after tuning;
+                                   NULL: keep results in memory only */
+    int32_t tune;               /* 1: at plan creation, time the candidate spreader
+                                   configurations (parts, flush period, fused or staged) of
+                                   every shape (precision, kernel width, grid size, samples)
+                                   on a small synthetic batch and use the fastest */
+    int32_t flush_period;       /* steps between collective flushes of the spreader (1..64,
+                                   power of two); 0: chosen from the sample density */
 } nr_options;
 
 typedef struct {
@@ -134,7 +144,7 @@ typedef struct {
     int64_t workspace_bytes; /* device bytes owned by the plan */
     int32_t n_classes;       /* kernel classes (precision, kernel width, grid size, parts) */
     int32_t out_fp64;        /* 1: outputs are double / complex double; 0: float */
-    int32_t method;          /* nr_method actually used */
+    int32_t method;          /* nr_method of the first class (classes may differ when tuned) */
     int32_t n_chunks;        /* launches per stage needed to cover the plan */
 } nr_plan_info;
 
@@ -149,6 +159,8 @@ typedef struct {
     double beta_es;     /* ES shape parameter */
     int64_t n_inst;     /* valid instances in the class */
     int64_t n_points;   /* sum of L over them */
+    int32_t method;          /* NR_METHOD_STAGED or NR_METHOD_FUSED */
+    int32_t flush_period;    /* spreader steps between collective flushes */
     int64_t series_terms;    /* sum over instances of L x (degree of the tau series) */
     int64_t fallback_points; /* samples of instances using the log1p/expm1 form of tau */
 } nr_class_info;

@@ -481,15 +481,34 @@ __device__ __forceinline__ void dft_small(cpx<T>* v, int R)
     }
 }
 
+// Lanes cooperating on one transform: 16 for grids up to 128 points (sixteen
+// transforms per workgroup), one wave up to 512, the whole workgroup above
+// (which keeps the LDS of the largest grids within one workgroup).
+__host__ __device__ __forceinline__ int team_size_for(int n) { return n <= 128 ? 16 : (n <= 512 ? kWave : kBlock); }
+
+// Synchronise the lanes of a team: teams inside one wave only need their LDS
+// writes completed (the wave runs in lockstep); larger teams use the
+// workgroup barrier.  Uniform across the workgroup.
+__device__ __forceinline__ void team_sync(int ts)
+{
+    if (ts > kWave) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
 // Stockham autosort FFT of the team's n points (ping-pong between buf[0..n)
 // and buf[n..2n)).  Pass with radix R and span Ns (product of the earlier
 // radices): butterfly j (0 <= j < n/R) takes inputs j + r n/R, applies the
 // twiddles exp(-2 pi i r k / (Ns R)) with k = j mod Ns, and writes output q
-// to (j / Ns) Ns R + k + q Ns.  Every thread of the block runs every pass.
-// Returns the buffer holding the result.
+// to (j / Ns) Ns R + k + q Ns.  tw is the LDS copy of exp(-2 pi i t / n).
+// Every lane of the workgroup runs every pass.  Returns the buffer holding
+// the result.
 template <typename T>
-__device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* __restrict__ tw, const FftPlanDev& fp,
-                            int tid, int ts)
+__device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* tw, const FftPlanDev& fp, int tid, int ts)
 {
     const int n = fp.n;
     cpx<T>* src = buf;
@@ -508,7 +527,7 @@ __device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* __restrict__ tw, const Ff
             const int base = (j / Ns) * Ns * R + k;
             for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
         }
-        __syncthreads();
+        team_sync(ts);
         cpx<T>* t = src;
         src = dst;
         dst = t;
@@ -517,10 +536,15 @@ __device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* __restrict__ tw, const Ff
     return src;
 }
 
+// LDS layout of the epilogue kernels: twiddles [n], then per team 2n points,
+// then (segment sum) per team kmax FP64 partial sums.
 template <typename T>
-__device__ __forceinline__ int team_size_for(int n)
+__device__ __forceinline__ cpx<T>* stage_twiddles(unsigned char* smem, const void* g, int n)
 {
-    return n <= 512 ? kWave : kBlock;
+    cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem);
+    const cpx<T>* src = reinterpret_cast<const cpx<T>*>(g);
+    for (int t = threadIdx.x; t < n; t += kBlock) tw[t] = src[t];
+    return tw;
 }
 
 template <typename T, typename O>
@@ -528,17 +552,18 @@ __global__ __launch_bounds__(kBlock) void epilogue_spectra_kernel(EpilogueArgs a
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.fft.n;
-    const int ts = team_size_for<T>(n);
+    const int ts = team_size_for(n);
     const int team = threadIdx.x / ts, tid = threadIdx.x % ts;
     const int nteam = kBlock / ts;
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw) + (size_t)team * 2 * n;
+    const cpx<T>* tw = stage_twiddles<T>(smem_raw, a.twiddle, n);
+    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw) + n + (size_t)team * 2 * n;
     const int64_t item = (int64_t)blockIdx.x * nteam + team;
     const bool live = item < a.count;
     const cpx<T>* gsrc = reinterpret_cast<const cpx<T>*>(a.grid) + item * n;
     if (live)
         for (int c = tid; c < n; c += ts) buf[c] = gsrc[c];
     __syncthreads();
-    const cpx<T>* res = fft_team<T>(buf, reinterpret_cast<const cpx<T>*>(a.twiddle), a.fft, tid, ts);
+    const cpx<T>* res = fft_team<T>(buf, tw, a.fft, tid, ts);
     if (!live) return;
     const InstDev d = a.inst[a.first + item];
     const T* __restrict__ dec = reinterpret_cast<const T*>(a.dec);
@@ -562,13 +587,9 @@ __global__ __launch_bounds__(kBlock) void epilogue_sum_kernel(EpilogueArgs a, in
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.fft.n;
-    const int ts = team_size_for<T>(n);
+    const int ts = team_size_for(n);
     const int team = threadIdx.x / ts, tid = threadIdx.x % ts;
     const int nteam = kBlock / ts;
-    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw) + (size_t)team * 2 * n;
-    double* part = reinterpret_cast<double*>(reinterpret_cast<cpx<T>*>(smem_raw) + (size_t)nteam * 2 * n);
-    double* mine = part + (size_t)team * kmax;
-
     const int ct = a.tmpl_first + blockIdx.x;
     int64_t lo = a.tmpl_list_off[ct], hi = a.tmpl_list_off[ct + 1];
     // entries of this chunk: class instances in [first, first + count)
@@ -588,12 +609,15 @@ __global__ __launch_bounds__(kBlock) void epilogue_sum_kernel(EpilogueArgs a, in
         hi = l;
     }
     const int64_t cnt = hi - lo;
-    if (cnt <= 0) return;  // uniform across the block
+    if (cnt <= 0) return;  // uniform across the workgroup
+    const cpx<T>* tw = stage_twiddles<T>(smem_raw, a.twiddle, n);
+    cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw) + n + (size_t)team * 2 * n;
+    double* part = reinterpret_cast<double*>(reinterpret_cast<cpx<T>*>(smem_raw) + n + (size_t)nteam * 2 * n);
+    double* mine = part + (size_t)team * kmax;
     const InstDev d0 = a.inst[a.tmpl_list[lo]];
     const int K = d0.K;
     for (int k = tid; k < K; k += ts) mine[k] = 0.0;
 
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(a.twiddle);
     const T* __restrict__ dec = reinterpret_cast<const T*>(a.dec);
     const int64_t rounds = (cnt + nteam - 1) / nteam;
     for (int64_t r = 0; r < rounds; ++r) {
@@ -713,9 +737,8 @@ int phase_table_size(int fp64)
 
 size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode)
 {
-    const int ts = n <= 512 ? kWave : kBlock;
-    const int nteam = kBlock / ts;
-    size_t b = (size_t)nteam * 2 * n * (fp64 ? 16 : 8);
+    const int nteam = kBlock / team_size_for(n);
+    size_t b = ((size_t)nteam * 2 + 1) * n * (fp64 ? 16 : 8);
     if (sum_mode) b += (size_t)nteam * K_max * 8;
     return b;
 }
@@ -801,7 +824,7 @@ hipError_t launch_epilogue_spectra(const EpilogueArgs& a, int fp64, int out_fp64
 {
     if (a.count <= 0) return hipSuccess;
     const int n = a.fft.n;
-    const int nteam = kBlock / (n <= 512 ? kWave : kBlock);
+    const int nteam = kBlock / team_size_for(n);
     dim3 grid((unsigned)((a.count + nteam - 1) / nteam)), block(kBlock);
     const size_t lds = epilogue_lds_bytes(fp64, n, 0, 0);
     if (fp64) {

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <random>
 #include <memory>
 #include <new>
 #include <stdexcept>
@@ -74,6 +76,7 @@ struct Chunk {
 
 struct Class {
     int fp64, w, n, deg, parts;
+    int method = NR_METHOD_FUSED;
     double beta_es;
     std::vector<int> radix;
     std::vector<InstDev> inst;         // class instances, ascending plan index
@@ -118,8 +121,16 @@ struct nr_plan_s {
     };
     std::vector<Timed> timed;
     std::vector<hipEvent_t> event_pool;
+    // captured launch sequences, keyed by call kind and pointer arguments
+    struct Graph {
+        int kind;
+        const void* key[5];
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
     ~nr_plan_s()
     {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
         for (auto& t : timed) {
             (void)hipEventDestroy(t.a);
             (void)hipEventDestroy(t.b);
@@ -147,6 +158,8 @@ void validate(const nr_segment* segs, int32_t n_segs, const nr_template* tmpls, 
     if (o.parts != 0 && o.parts != 1 && o.parts != 2 && o.parts != 4)
         fail(NR_ERR_INVALID_ARG, "parts must be 0, 1, 2 or 4");
     if (o.strain_length < 0 || o.max_workspace_bytes < 0) fail(NR_ERR_INVALID_ARG, "negative size option");
+    if (o.flush_period < 0 || o.flush_period > 64 || (o.flush_period & (o.flush_period - 1)))
+        fail(NR_ERR_INVALID_ARG, "flush_period must be 0 or a power of two up to 64");
     for (int32_t s = 0; s < n_segs; ++s) {
         const nr_segment& g = segs[s];
         if (g.n_samples < 1 || g.n_samples > (int64_t(1) << 30))
@@ -268,12 +281,60 @@ int default_parts(int64_t L)
 }
 
 struct ClassKey {
-    int fp64, w, n, parts;
+    int fp64, w, n, parts, method, flush;
     bool operator<(const ClassKey& o) const
     {
-        return std::tie(fp64, w, n, parts) < std::tie(o.fp64, o.w, o.n, o.parts);
+        return std::tie(fp64, w, n, parts, method, flush) < std::tie(o.fp64, o.w, o.n, o.parts, o.method, o.flush);
     }
 };
+
+// ------------------------------------------------------------- autotuner --
+
+// Spreader configuration of one shape (precision, kernel width, grid, samples).
+struct Tuned {
+    int method, parts, flush;
+    double us_per_inst;
+};
+struct ShapeKey {
+    int fp64, w, n;
+    int64_t L;
+    bool operator<(const ShapeKey& o) const { return std::tie(fp64, w, n, L) < std::tie(o.fp64, o.w, o.n, o.L); }
+};
+
+std::mutex g_tune_mutex;
+std::map<ShapeKey, Tuned> g_tuned;             // process-wide results
+std::map<std::string, bool> g_cache_loaded;    // cache files already read
+
+void load_tune_cache(const char* path)
+{
+    if (!path || g_cache_loaded[path]) return;
+    g_cache_loaded[path] = true;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    ShapeKey k;
+    Tuned t;
+    long long L;
+    while (std::fscanf(f, "%d %d %d %lld %d %d %d %lf", &k.fp64, &k.w, &k.n, &L, &t.method, &t.parts, &t.flush,
+                       &t.us_per_inst) == 8) {
+        k.L = L;
+        g_tuned[k] = t;
+    }
+    std::fclose(f);
+}
+
+void save_tune_cache(const char* path)
+{
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto& kv : g_tuned)
+        std::fprintf(f, "%d %d %d %lld %d %d %d %.6f\n", kv.first.fp64, kv.first.w, kv.first.n,
+                     (long long)kv.first.L, kv.second.method, kv.second.parts, kv.second.flush,
+                     kv.second.us_per_inst);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
 
 template <typename T>
 std::vector<T> cast_vec(const std::vector<long double>& v)
@@ -322,6 +383,9 @@ void build_class_tables(Class& c, double tol_cls, double sigma)
     }
     (void)sigma;
 }
+
+Tuned tuned_config(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
+                   int w, int n);
 
 void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_template* tmpls,
                  int32_t n_tmpls, const nr_instance* inst, int64_t n_inst, double tol)
@@ -381,7 +445,9 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         int lo = 1, hi = 1 << 16;
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
-            if (spread_lds_bytes(f, mid) <= kLdsBytes) lo = mid; else hi = mid - 1;
+            const bool fits = spread_lds_bytes(f, mid) <= kLdsBytes &&
+                              epilogue_lds_bytes(f, mid, mid, 1) <= kLdsBytes;
+            if (fits) lo = mid; else hi = mid - 1;
         }
         n_max_of[f] = lo;
     }
@@ -389,7 +455,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     for (int32_t m = 0; m < n_tmpls; ++m) tmpl_beta[m] = chirp_beta(P.tmpls[m].mc_msun, P.tmpls[m].f0);
     // kernel width per distinct tolerance, and the last class looked up
     std::map<std::pair<double, int>, int> width_of;
-    ClassKey last_key{-1, -1, -1, -1};
+    ClassKey last_key{-1, -1, -1, -1, -1, -1};
     size_t last_ci = 0;
     for (int64_t i = 0; i < N; ++i) {
         const nr_segment& g = P.segs[P.inst_seg[i]];
@@ -419,8 +485,16 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": grid size " + std::to_string(n) +
                                          " exceeds the supported maximum " + std::to_string(n_max) +
                                          " (lower n_bins or sigma)");
-        const int parts = o.parts ? o.parts : default_parts(g.n_samples);
-        ClassKey key{fp64, w, n, parts};
+        int parts = o.parts ? o.parts : default_parts(g.n_samples);
+        int method = (o.method == NR_METHOD_STAGED) ? NR_METHOD_STAGED : NR_METHOD_FUSED;
+        int flush = o.flush_period;
+        if (o.tune) {
+            const Tuned tu = tuned_config(o, g, t, tol_eff, fp64, w, n);
+            parts = tu.parts;
+            method = tu.method;
+            flush = tu.flush;
+        }
+        ClassKey key{fp64, w, n, parts, method, flush};
         size_t ci;
         const bool same = !(key < last_key) && !(last_key < key);
         auto it = same ? class_of.end() : class_of.find(key);
@@ -436,6 +510,8 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             c->w = w;
             c->n = n;
             c->parts = parts;
+            c->method = method;
+            c->flush_period = flush;
             c->beta_es = es_beta(w, sigma);
             P.classes.push_back(std::move(c));
         } else {
@@ -514,7 +590,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             c.tmpl_list_off.push_back((int64_t)c.tmpl_list.size());
         }
         // collective flush period: about half the samples a lane spends in one cell
-        {
+        if (c.flush_period <= 0) {
             long double pts_per_cell = 0.0L;
             for (const InstDev& d : c.inst) {
                 const long double span = std::max(1.0L, (long double)d.df * d.L / (long double)P.segs[d.seg].fs);
@@ -532,7 +608,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         fixed_bytes += c.strain_entries * esize;
         // chunks bounded by the workspace cap
         const int64_t gsize = (int64_t)c.n * (c.fp64 ? 16 : 8);
-        const int64_t psz = P.method == NR_METHOD_STAGED ? (c.fp64 ? psize_d : psize_f) : 0;
+        const int64_t psz = c.method == NR_METHOD_STAGED ? (c.fp64 ? psize_d : psize_f) : 0;
         const int64_t budget = std::max<int64_t>(cap / 2, 1);
         int64_t k0 = 0;
         while (k0 < (int64_t)c.inst.size()) {
@@ -572,7 +648,8 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         fail(NR_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(fixed_bytes + grid_chunk_bytes + point_chunk_bytes) +
                                        " bytes exceeds max_workspace_bytes " + std::to_string(cap));
     P.d_grid.alloc((size_t)grid_chunk_bytes, "grid");
-    if (P.method == NR_METHOD_STAGED) P.d_points.alloc((size_t)point_chunk_bytes, "point stream");
+    if (point_chunk_bytes > 0) P.d_points.alloc((size_t)point_chunk_bytes, "point stream");
+    if (!P.classes.empty()) P.method = P.classes[0]->method;
     P.d_mask.upload(P.valid, "mask");
     std::vector<int32_t> invalid;
     for (int64_t i = 0; i < N; ++i)
@@ -674,10 +751,10 @@ void check_finite(nr_plan_s& P, const void* strain)
 void run_front(nr_plan_s& P, Class& c, const Chunk& ch)
 {
     SpreadArgs a = spread_args(P, c, ch);
-    if (P.method == NR_METHOD_STAGED)
+    if (c.method == NR_METHOD_STAGED)
         timed_launch(P, NR_STAGE_TAU, [&] { return launch_tau(a, c.fp64, P.stream); }, "tau kernel");
     timed_launch(P, NR_STAGE_SPREAD,
-                 [&] { return launch_spread(a, c.fp64, c.deg, P.method == NR_METHOD_FUSED, P.stream); },
+                 [&] { return launch_spread(a, c.fp64, c.deg, c.method == NR_METHOD_FUSED, P.stream); },
                  "spread kernel");
 }
 
@@ -689,10 +766,59 @@ void lane_major(nr_plan_s& P, Class& c, const void* strain)
     }, "strain layout");
 }
 
+void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid);
+
+// Run enqueue() directly, or through a HIP graph captured on the first call
+// with these pointer arguments and replayed afterwards.
+template <typename F>
+void run_graphed(nr_plan_s& P, int kind, std::initializer_list<const void*> args, F&& enqueue)
+{
+    const bool can = P.opt.use_graph && P.stream != nullptr && !P.opt.profile && !P.opt.check_finite;
+    if (!can) {
+        enqueue();
+        return;
+    }
+    const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    int k = 0;
+    for (const void* a : args) key[k++] = a;
+    for (auto& g : P.graphs)
+        if (g.kind == kind && std::equal(key, key + 5, g.key)) {
+            hip_check(hipGraphLaunch(g.exec, P.stream), "graph launch");
+            return;
+        }
+    hip_check(hipStreamBeginCapture(P.stream, hipStreamCaptureModeRelaxed), "begin capture");
+    hipGraph_t graph = nullptr;
+    try {
+        enqueue();
+    } catch (...) {
+        (void)hipStreamEndCapture(P.stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    hip_check(hipStreamEndCapture(P.stream, &graph), "end capture");
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    hip_check(e, "graph instantiate");
+    if (P.graphs.size() >= 8) {
+        (void)hipGraphExecDestroy(P.graphs.front().exec);
+        P.graphs.erase(P.graphs.begin());
+    }
+    nr_plan_s::Graph g{kind, {}, exec};
+    std::copy(key, key + 5, g.key);
+    P.graphs.push_back(g);
+    hip_check(hipGraphLaunch(exec, P.stream), "graph launch");
+}
+
 void execute(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid)
 {
     if (!strain) fail(NR_ERR_INVALID_ARG, "strain is NULL");
     check_finite(P, strain);
+    run_graphed(P, 0, {strain, spectra, power, valid}, [&] { execute_launches(P, strain, spectra, power, valid); });
+}
+
+void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid)
+{
     for (auto& cp : P.classes) {
         Class& c = *cp;
         lane_major(P, c, strain);
@@ -715,10 +841,17 @@ void execute(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8
         }, "invalid fill");
 }
 
+void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, void* stat, int32_t* n_used);
+
 void semicoherent(nr_plan_s& P, const void* strain, const double* w, void* stat, int32_t* n_used)
 {
     if (!strain || !stat) fail(NR_ERR_INVALID_ARG, "strain and stat must not be NULL");
     check_finite(P, strain);
+    run_graphed(P, 1, {strain, w, stat, n_used}, [&] { semicoherent_launches(P, strain, w, stat, n_used); });
+}
+
+void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, void* stat, int32_t* n_used)
+{
     for (auto& cp : P.classes) {
         Class& c = *cp;
         lane_major(P, c, strain);
@@ -732,6 +865,91 @@ void semicoherent(nr_plan_s& P, const void* strain, const double* w, void* stat,
                          [&] { return launch_epilogue_sum(e, c.fp64, P.out_fp64, P.stream); }, "segment sum");
         }
     }
+}
+
+// Time one spreader configuration on a synthetic batch of identical instances.
+double time_config(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
+                   int method, int parts, int flush, const void* strain, void* stat, int32_t* used, int64_t batch)
+{
+    nr_options o2 = base;
+    o2.tune = 0;
+    o2.tune_cache = nullptr;
+    o2.parts = parts;
+    o2.flush_period = flush;
+    o2.method = method;
+    o2.precision = fp64 ? NR_FP64 : NR_FP32;
+    o2.profile = 0;
+    o2.use_graph = 0;
+    o2.check_finite = 0;
+    o2.strain_length = 0;
+    o2.max_workspace_bytes = 0;
+    nr_segment s1 = g;
+    s1.sample_offset = 0;
+    std::vector<nr_instance> il((size_t)batch, nr_instance{0, 0, tol});
+    nr_plan_s mini;
+    mini.opt = o2;
+    create_plan(mini, &s1, 1, &t, 1, il.data(), batch, tol);
+    semicoherent(mini, strain, nullptr, stat, used);  // warm-up
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "event");
+    hip_check(hipEventCreate(&b), "event");
+    hip_check(hipEventRecord(a, mini.stream), "event");
+    for (int r = 0; r < 3; ++r) semicoherent(mini, strain, nullptr, stat, used);
+    hip_check(hipEventRecord(b, mini.stream), "event");
+    hip_check(hipEventSynchronize(b), "event");
+    float ms = 0.0f;
+    hip_check(hipEventElapsedTime(&ms, a, b), "event");
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return 1e3 * ms / 3.0 / (double)batch;
+}
+
+Tuned tune_shape(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64)
+{
+    const int64_t L = g.n_samples;
+    int64_t batch = (int64_t(1) << 25) / std::max<int64_t>(L, 1);
+    batch = std::min<int64_t>(4096, std::max<int64_t>(256, batch));
+    // synthetic N(0,1) strain (values do not change the cost)
+    std::mt19937_64 rng(12345);
+    std::normal_distribution<double> nd;
+    DevBuf strain, stat, used;
+    if (fp64) {
+        std::vector<double> h((size_t)L);
+        for (auto& v : h) v = nd(rng);
+        strain.upload(h, "tuning strain");
+    } else {
+        std::vector<float> h((size_t)L);
+        for (auto& v : h) v = (float)nd(rng);
+        strain.upload(h, "tuning strain");
+    }
+    stat.alloc((size_t)t.n_bins * 8, "tuning output");
+    used.alloc(sizeof(int32_t), "tuning output");
+    hip_check(hipMemset(stat.p, 0, (size_t)t.n_bins * 8), "tuning output");
+    Tuned best{NR_METHOD_FUSED, default_parts(L), 0, INFINITY};
+    for (int method : {NR_METHOD_FUSED, NR_METHOD_STAGED})
+        for (int parts : {1, 2, 4}) {
+            if (parts > 1 && L < (int64_t)kWave * parts * 16) continue;
+            for (int flush : {4, 16, 64}) {
+                const double us = time_config(base, g, t, tol, fp64, method, parts, flush, strain.p, stat.p,
+                                              (int32_t*)used.p, batch);
+                if (us < best.us_per_inst) best = Tuned{method, parts, flush, us};
+            }
+        }
+    return best;
+}
+
+Tuned tuned_config(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
+                   int w, int n)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    load_tune_cache(base.tune_cache);
+    const ShapeKey key{fp64, w, n, g.n_samples};
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+    const Tuned tu = tune_shape(base, g, t, tol, fp64);
+    g_tuned[key] = tu;
+    save_tune_cache(base.tune_cache);
+    return tu;
 }
 
 template <typename F>
@@ -861,6 +1079,8 @@ nr_status nufft_resample_query_class(nr_plan p, int32_t ci, nr_class_info* info)
     info->n_radix = (int32_t)c.radix.size();
     for (size_t r = 0; r < c.radix.size() && r < 8; ++r) info->radix[r] = c.radix[r];
     info->beta_es = c.beta_es;
+    info->method = c.method;
+    info->flush_period = c.flush_period;
     info->n_inst = (int64_t)c.inst.size();
     info->n_points = c.n_points;
     for (const InstDev& d : c.inst) {

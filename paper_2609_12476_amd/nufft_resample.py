@@ -42,9 +42,10 @@ class NrInstance(ctypes.Structure):
 class NrOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("method", c_int32), ("sigma", c_double),
                 ("strain_complex", c_int32), ("strict", c_int32), ("check_finite", c_int32),
-                ("parts", c_int32), ("profile", c_int32), ("reserved", c_int32),
+                ("parts", c_int32), ("profile", c_int32), ("use_graph", c_int32),
                 ("strain_length", c_int64), ("max_workspace_bytes", c_int64),
-                ("stream", c_void_p), ("tune_cache", c_char_p)]
+                ("stream", c_void_p), ("tune_cache", c_char_p), ("tune", c_int32),
+                ("flush_period", c_int32)]
 
 
 class NrPlanInfo(ctypes.Structure):
@@ -65,6 +66,7 @@ class NrClassInfo(ctypes.Structure):
     _fields_ = [("fp64", c_int32), ("w", c_int32), ("n", c_int32), ("degree", c_int32),
                 ("parts", c_int32), ("n_radix", c_int32), ("radix", c_int32 * 8),
                 ("beta_es", c_double), ("n_inst", c_int64), ("n_points", c_int64),
+                ("method", c_int32), ("flush_period", c_int32),
                 ("series_terms", c_int64), ("fallback_points", c_int64)]
 
 
@@ -214,30 +216,49 @@ def nufft_resample_destroy(plan):
 # Convenience wrapper
 # ----------------------------------------------------------------------------
 
-def make_segments(seg_offset, seg_len, seg_fs, seg_t):
-    n = len(seg_offset)
-    arr = (NrSegment * n)()
-    for i in range(n):
-        arr[i] = NrSegment(int(seg_offset[i]), int(seg_len[i]), float(seg_fs[i]), float(seg_t[i]))
+def _struct_array(ctype, n, fields):
+    """ctypes array of n ctype structs filled column-wise from numpy arrays."""
+    arr = (ctype * n)()
+    raw = np.frombuffer(arr, dtype=np.uint8)
+    view = raw.view(_numpy_dtype(ctype))
+    for name, values in fields.items():
+        view[name] = values
     return arr
+
+
+_DTYPES = {}
+
+
+def _numpy_dtype(ctype):
+    if ctype not in _DTYPES:
+        names, formats, offsets = [], [], []
+        for name, ft in ctype._fields_:
+            names.append(name)
+            formats.append(np.dtype(ft))
+            offsets.append(getattr(ctype, name).offset)
+        _DTYPES[ctype] = np.dtype({"names": names, "formats": formats, "offsets": offsets,
+                                   "itemsize": ctypes.sizeof(ctype)})
+    return _DTYPES[ctype]
+
+
+def make_segments(seg_offset, seg_len, seg_fs, seg_t):
+    return _struct_array(NrSegment, len(seg_offset), {
+        "sample_offset": np.asarray(seg_offset, np.int64), "n_samples": np.asarray(seg_len, np.int64),
+        "fs": np.asarray(seg_fs, np.float64), "t_start": np.asarray(seg_t, np.float64)})
 
 
 def make_templates(mc, f0, f_lo, df, n_bins, f_max):
-    n = len(mc)
-    arr = (NrTemplate * n)()
-    for i in range(n):
-        arr[i] = NrTemplate(float(mc[i]), float(f0[i]), float(f_lo[i]), float(df[i]),
-                            int(n_bins[i]), 0, float(f_max[i]))
-    return arr
+    return _struct_array(NrTemplate, len(mc), {
+        "mc_msun": np.asarray(mc, np.float64), "f0": np.asarray(f0, np.float64),
+        "f_lo": np.asarray(f_lo, np.float64), "df": np.asarray(df, np.float64),
+        "n_bins": np.asarray(n_bins, np.int32), "f_max": np.asarray(f_max, np.float64)})
 
 
 def make_instances(inst_seg, inst_tmpl, inst_tol=None):
     n = len(inst_seg)
-    arr = (NrInstance * n)()
-    for i in range(n):
-        arr[i] = NrInstance(int(inst_seg[i]), int(inst_tmpl[i]),
-                            float(inst_tol[i]) if inst_tol is not None else 0.0)
-    return arr
+    return _struct_array(NrInstance, n, {
+        "segment": np.asarray(inst_seg, np.int32), "template_id": np.asarray(inst_tmpl, np.int32),
+        "tol": np.zeros(n) if inst_tol is None else np.asarray(inst_tol, np.float64)})
 
 
 class Plan:
@@ -249,7 +270,8 @@ class Plan:
 
     def __init__(self, segs, tmpls, inst=None, tol=1e-6, precision="fp32", method="auto",
                  sigma=2.0, strict=False, parts=0, strain_complex=False, strain_length=0,
-                 max_workspace_bytes=0, check_finite=False, profile=False, stream=None):
+                 max_workspace_bytes=0, check_finite=False, profile=False, use_graph=False,
+                 tune=False, tune_cache=None, flush_period=0, stream=None):
         import torch
         opt = nufft_resample_default_options()
         opt.precision = _PRECISION[precision]
@@ -262,6 +284,11 @@ class Plan:
         opt.max_workspace_bytes = int(max_workspace_bytes)
         opt.check_finite = int(bool(check_finite))
         opt.profile = int(bool(profile))
+        opt.use_graph = int(bool(use_graph))
+        opt.tune = int(bool(tune))
+        opt.flush_period = int(flush_period)
+        self._tune_cache = tune_cache.encode() if tune_cache else None
+        opt.tune_cache = self._tune_cache
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         self.stream = stream

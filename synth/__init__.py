@@ -318,3 +318,29 @@ def mlp_init_params(seed):
             lim = math.sqrt(6.0 / fan_in)
             parts.append(rng.uniform(-lim, lim, size=shape))
     return np.concatenate([q.ravel() for q in parts]).astype(np.float32)
+
+
+def beta_bank(n_beta=69, beta_lo=3e-8, beta_hi=7e-4, f0=50.0):
+    """Chirp masses of a bank uniform in beta (Sec. III.A: 69 templates over
+    3e-8 <= beta <= 7e-4), expressed at the template frequency f0:
+    Mc = (beta / ((96/5) pi^{8/3} T_sun^{5/3} f0^{8/3}))^{3/5}."""
+    betas = np.linspace(beta_lo, beta_hi, n_beta)
+    c = (96.0 / 5.0) * math.pi ** (8.0 / 3.0) * T_SUN ** (5.0 / 3.0) * f0 ** (8.0 / 3.0)
+    return betas, (betas / c) ** 0.6
+
+
+def paper_bank(hours=1.0, seed=5, fs=512.0, t_coh=30.0, n_beta=69):
+    """The paper's coherent workload (Sec. VI): 30 s segments resampled at 512 Hz,
+    69 beta templates uniform over [3e-8, 7e-4] at f0 = 50 Hz, the full 40-60 Hz
+    band as 600 bins of 1/30 Hz; N(0,1) noise (no injection)."""
+    L = int(round(t_coh * fs))
+    n_seg = int(round(hours * 3600.0 / t_coh))
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(n_seg * L)
+    off, ln, fsa, ts = _segments(n_seg, L, fs)
+    _, mc = beta_bank(n_beta)
+    m = len(mc)
+    return Workload(name=f"paper_beta_bank_{hours:g}h_{n_beta}beta_512Hz", strain=x,
+                    seg_offset=off, seg_len=ln, seg_fs=fsa, seg_t=ts,
+                    mc=mc, f0=np.full(m, 50.0), f_lo=np.full(m, BAND_LO), df=np.full(m, 1.0 / t_coh),
+                    n_bins=np.full(m, 600, np.int32), f_max=np.zeros(m), tol=1e-6)

@@ -231,3 +231,64 @@ def test_invalid_instances_are_zero_and_flagged(gpu):
     assert np.array_equal(valid, ok)
     errs = per_instance_errors(X, Xr, off, ok)
     assert errs.max() <= FP32_SPEC
+
+
+def test_graph_replay_matches_eager(gpu):
+    say("graph replay")
+    import torch
+    from paper_2609_12476_amd import Plan
+    w = synth.semicoherent(hours=0.1, n_mc=4, n_sub=3, seed=13)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        pe = Plan.from_workload(w, precision="fp32", tol=1e-6, stream=s)
+        pg = Plan.from_workload(w, precision="fp32", tol=1e-6, stream=s, use_graph=True)
+        x = pe.strain_tensor(w.strain, gpu)
+        sp_e, pw_e, v_e = pe.execute(x)
+        st_e, u_e = pe.semicoherent_sum(x)
+        s.synchronize()
+        sp_g, pw_g, v_g = torch.empty_like(sp_e), torch.empty_like(pw_e), torch.empty_like(v_e)
+        st_g, u_g = torch.zeros_like(st_e), torch.zeros_like(u_e)
+        for rep in range(4):
+            # the program's own eager work between replays
+            sp_g.fill_(-1.0)
+            pw_g.fill_(-1.0)
+            v_g.fill_(7)
+            st_g.zero_()
+            u_g.zero_()
+            pg.execute(x, sp_g, pw_g, v_g)
+            pg.semicoherent_sum(x, None, st_g, u_g)
+            s.synchronize()
+            assert torch.equal(sp_g, sp_e) and torch.equal(pw_g, pw_e) and torch.equal(v_g, v_e), rep
+            assert torch.equal(st_g, st_e) and torch.equal(u_g, u_e), rep
+        pe.close()
+        pg.close()
+
+
+def test_autotuned_plan_parity_and_cache(gpu, tmp_path):
+    say("autotuner")
+    w = synth.ragged_batch(n_inst=12, seed=31)
+    Xr, off, ok = oracle.spectra(w)
+    cache = str(tmp_path / "tune.txt")
+    X, _, _, _, cls = run_plan(w, gpu, precision="auto", tune=True, tune_cache=cache)
+    lines = open(cache).read().split("\n")
+    assert len([l for l in lines if l.strip()]) >= 1
+    say(f"  tuned classes: {[(c.fp64, c.w, c.n, c.parts, c.method, c.flush_period) for c in cls]}")
+    for i in range(w.n_inst):
+        if ok[i]:
+            t = w.inst_tol[i]
+            bound = max(t, FP32_SPEC) if t >= 1e-6 else max(t, 1e-11)
+            assert rel(X[off[i]:off[i + 1]], Xr[off[i]:off[i + 1]]) <= bound
+    # a second plan reads the cache and picks the same configurations
+    _, _, _, _, cls2 = run_plan(w, gpu, precision="auto", tune=True, tune_cache=cache)
+    assert [(c.parts, c.method, c.flush_period) for c in cls] == [(c.parts, c.method, c.flush_period) for c in cls2]
+
+
+@pytest.mark.parametrize("flush", [1, 8, 64])
+def test_forced_flush_period(gpu, flush):
+    say(f"flush period {flush}")
+    w = synth.semicoherent(hours=0.05, n_mc=2, n_sub=2, seed=14)
+    Xr, off, ok = oracle.spectra(w)
+    X, _, _, _, cls = run_plan(w, gpu, precision="fp64", tol=1e-10, flush_period=flush)
+    assert cls[0].flush_period == flush
+    errs = per_instance_errors(X, Xr, off, ok)
+    assert errs.max() <= FP64_SPEC
