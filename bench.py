@@ -58,6 +58,8 @@ def parse():
                     choices=["semicoherent_1h", "full_sweep_6h", "ragged_512", "paper_beta_bank"],
                     help="semicoherent_1h is the headline; the others print their own line")
     ap.add_argument("--tune", action="store_true", help="autotune the spreader per shape")
+    ap.add_argument("--moment-mode", type=int, default=0, help="0 auto, 1 per cell, 2 cumulative")
+    ap.add_argument("--flush-period", type=int, default=0)
     return ap.parse_args()
 
 
@@ -188,7 +190,8 @@ def main():
     log("generating workload")
     w = synth.semicoherent(hours=args.hours, n_mc=args.n_mc, n_sub=20, seed=1, tol=1e-6)
     w32 = w.as_float32_strain()           # the FP32 path's input values; the FP64 runs use the same
-    plan = Plan.from_workload(w32, tol=1e-6, precision="fp32", method=args.method, profile=True)
+    plan = Plan.from_workload(w32, tol=1e-6, precision="fp32", method=args.method, profile=True,
+                              moment_mode=args.moment_mode, flush_period=args.flush_period, tune=args.tune)
     info = plan.info
     cls = plan.classes()
     x32 = plan.strain_tensor(w32.strain, dev)

@@ -133,6 +133,9 @@ typedef struct {
                                    on a small synthetic batch and use the fastest */
     int32_t flush_period;       /* steps between collective flushes of the spreader (1..64,
                                    power of two); 0: chosen from the sample density */
+    int32_t moment_mode;        /* spreader moments: 0 automatic, 1 restarted per grid cell,
+                                   2 cumulative with snapshots (FP32 classes, degree <= 12) */
+    int32_t reserved2;
 } nr_options;
 
 typedef struct {
@@ -161,6 +164,8 @@ typedef struct {
     int64_t n_points;   /* sum of L over them */
     int32_t method;          /* NR_METHOD_STAGED or NR_METHOD_FUSED */
     int32_t flush_period;    /* spreader steps between collective flushes */
+    int32_t snap;            /* 1: cumulative spreader moments with snapshots; 0: per cell */
+    int32_t reserved;
     int64_t series_terms;    /* sum over instances of L x (degree of the tau series) */
     int64_t fallback_points; /* samples of instances using the log1p/expm1 form of tau */
 } nr_class_info;

@@ -69,7 +69,7 @@ struct SpreadArgs {
     int32_t parts;           // waves per instance (1, 2 or 4)
     int32_t flush_period;    // steps between collective flushes (power of two)
     int32_t strain_complex;
-    int32_t pad_;
+    int32_t snap;            // 1: cumulative moments with snapshots; 0: per-cell moments
 };
 
 struct EpilogueArgs {

@@ -215,8 +215,9 @@ __device__ __forceinline__ Decoded<T> decode(Reduced r, T xr, T xi, int n, const
     Decoded<T> o;
     const double S = r.pos * (double)n;           // (x - w/2) mod n, in cells
     const double fl = floor(S);
+    // in [1, n + 1]; n + 1 (S rounded up to n) is cell 1 again, which the
+    // flush's single modulo step maps correctly
     o.g = (int)fl + 1;
-    if (o.g > n) o.g -= n;  // S rounded up to n, which is cell position 0
     o.u = (T)fma(-2.0, S - fl, 1.0);
     // phase = k / N + theta / (2 pi), |theta| <= pi / N
     constexpr int B = PhaseTable<T>::bits;
@@ -308,16 +309,35 @@ __device__ __forceinline__ void flush(const Moments<T, D>& M, int g, const T* __
     }
 }
 
+// Flush the difference of two cumulative moment snapshots.
+template <typename T, int D>
+__device__ __forceinline__ void flush_diff(const Moments<T, D>& E, const Moments<T, D>& P, int g,
+                                           const T* __restrict__ A, cpx<T>* grid, int n, int w)
+{
+    Moments<T, D> V;
+#pragma unroll
+    for (int p = 0; p <= D; ++p) {
+        V.re[p] = E.re[p] - P.re[p];
+        V.im[p] = E.im[p] - P.im[p];
+    }
+    flush<T, D>(V, g, A, grid, n, w);
+}
+
 // One wave per (instance, part).  Each lane walks its run of samples in
 // order; because tau is monotone in t the support's first cell g only
 // moves forward (and wraps once per period), so a lane keeps the Chebyshev
 // moments of the points sharing one g and turns them into kernel taps only
-// when g changes.  A change parks the finished moments; parked moments are
+// when g changes.  A change parks the finished cell; parked cells are
 // flushed by the whole wave every flush_period steps (or at once if a lane
-// changes cell twice within a period).  Each wave owns its grid copy, so
-// the LDS additions of one grid come from one wave in program order and the
-// result does not depend on scheduling.
-template <typename T, int D, bool FUSED, bool CPLX>
+// changes cell twice within a period).
+//   SNAP = false: the moments restart at zero for every cell and the
+//                 finished ones are parked (copied) aside.
+//   SNAP = true:  the moments are cumulative over the lane's run; a change
+//                 only copies them into a snapshot, and a flush turns the
+//                 difference of two snapshots into taps.
+// Each wave owns its grid copy, so the LDS additions of one grid come from
+// one wave in program order and the result does not depend on scheduling.
+template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
 __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
 {
     using P = typename PointOf<T>::type;
@@ -355,9 +375,13 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
         const int64_t xs0 = d.strain_off + row0;
         const int fmask = a.flush_period - 1;
 
-        Moments<T, D> M, Sv;
+        // SNAP: M cumulative, E = snapshot at the end of the parked cell,
+        //       S = snapshot at its start.
+        // otherwise: M for the current cell, E = the parked cell's moments.
+        Moments<T, D> M, E, S;
         M.zero();
-        Sv.zero();
+        E.zero();
+        if (SNAP) S.zero();
         int g_cur = -1, g_pend = -1;
         for (int s = 0; s < C; ++s) {
             const int j = v * C + s;
@@ -379,24 +403,44 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
                 const Decoded<T> q = decode<T, CPLX>(r, xr, xi, n, tab);
                 if (q.g != g_cur) {
                     if (g_cur >= 0) {
-                        if (g_pend >= 0) flush<T, D>(Sv, g_pend, A, grid, n, w);
-                        Sv = M;
+                        if (SNAP) {
+                            if (g_pend >= 0) {
+                                flush_diff<T, D>(E, S, g_pend, A, grid, n, w);
+                                S = E;
+                            }
+                        } else {
+                            if (g_pend >= 0) flush<T, D>(E, g_pend, A, grid, n, w);
+                        }
+                        E = M;
                         g_pend = g_cur;
                     }
-                    M.zero();
+                    if (!SNAP) M.zero();
                     g_cur = q.g;
                 }
                 M.add(q.u, q.cr, q.ci);
             }
             if ((s & fmask) == fmask) {
                 if (g_pend >= 0) {
-                    flush<T, D>(Sv, g_pend, A, grid, n, w);
+                    if (SNAP) {
+                        flush_diff<T, D>(E, S, g_pend, A, grid, n, w);
+                        S = E;
+                    } else {
+                        flush<T, D>(E, g_pend, A, grid, n, w);
+                    }
                     g_pend = -1;
                 }
             }
         }
-        if (g_pend >= 0) flush<T, D>(Sv, g_pend, A, grid, n, w);
-        if (g_cur >= 0) flush<T, D>(M, g_cur, A, grid, n, w);
+        if (SNAP) {
+            if (g_pend >= 0) {
+                flush_diff<T, D>(E, S, g_pend, A, grid, n, w);
+                S = E;
+            }
+            if (g_cur >= 0) flush_diff<T, D>(M, S, g_cur, A, grid, n, w);
+        } else {
+            if (g_pend >= 0) flush<T, D>(E, g_pend, A, grid, n, w);
+            if (g_cur >= 0) flush<T, D>(M, g_cur, A, grid, n, w);
+        }
     }
     __syncthreads();
 
@@ -776,11 +820,23 @@ hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T, int D, bool FUSED, bool CPLX>
+template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
 static void launch_spread_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStream_t st)
 {
-    allow_lds(spread_kernel<T, D, FUSED, CPLX>, lds);
-    spread_kernel<T, D, FUSED, CPLX><<<grid, dim3(kBlock), lds, st>>>(a);
+    allow_lds(spread_kernel<T, D, FUSED, CPLX, SNAP>, lds);
+    spread_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(a);
+}
+
+template <typename T, int D, bool SNAP>
+static void launch_spread_s(const SpreadArgs& a, int fused, dim3 grid, size_t lds, hipStream_t st)
+{
+    if (fused) {
+        if (a.strain_complex) launch_spread_k<T, D, true, true, SNAP>(a, grid, lds, st);
+        else launch_spread_k<T, D, true, false, SNAP>(a, grid, lds, st);
+    } else {
+        if (a.strain_complex) launch_spread_k<T, D, false, true, SNAP>(a, grid, lds, st);
+        else launch_spread_k<T, D, false, false, SNAP>(a, grid, lds, st);
+    }
 }
 
 template <typename T, int D>
@@ -789,13 +845,12 @@ static hipError_t launch_spread_d(const SpreadArgs& a, int fused, hipStream_t st
     const int64_t per_block = 4 / a.parts;
     dim3 grid((unsigned)((a.count + per_block - 1) / per_block));
     const size_t lds = spread_lds_bytes(sizeof(T) == 8, a.n);
-    if (fused) {
-        if (a.strain_complex) launch_spread_k<T, D, true, true>(a, grid, lds, st);
-        else launch_spread_k<T, D, true, false>(a, grid, lds, st);
-    } else {
-        if (a.strain_complex) launch_spread_k<T, D, false, true>(a, grid, lds, st);
-        else launch_spread_k<T, D, false, false>(a, grid, lds, st);
-    }
+    // cumulative snapshots need a third register set: FP32 classes of moderate degree only
+    constexpr bool snap_ok = sizeof(T) == 4 && D <= 12;
+    if (snap_ok && a.snap)
+        launch_spread_s<T, D, snap_ok>(a, fused, grid, lds, st);
+    else
+        launch_spread_s<T, D, false>(a, fused, grid, lds, st);
     return hipGetLastError();
 }
 

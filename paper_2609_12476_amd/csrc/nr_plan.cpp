@@ -77,6 +77,7 @@ struct Chunk {
 struct Class {
     int fp64, w, n, deg, parts;
     int method = NR_METHOD_FUSED;
+    int snap = 0;
     double beta_es;
     std::vector<int> radix;
     std::vector<InstDev> inst;         // class instances, ascending plan index
@@ -158,6 +159,7 @@ void validate(const nr_segment* segs, int32_t n_segs, const nr_template* tmpls, 
     if (o.parts != 0 && o.parts != 1 && o.parts != 2 && o.parts != 4)
         fail(NR_ERR_INVALID_ARG, "parts must be 0, 1, 2 or 4");
     if (o.strain_length < 0 || o.max_workspace_bytes < 0) fail(NR_ERR_INVALID_ARG, "negative size option");
+    if (o.moment_mode < 0 || o.moment_mode > 2) fail(NR_ERR_INVALID_ARG, "moment_mode must be 0, 1 or 2");
     if (o.flush_period < 0 || o.flush_period > 64 || (o.flush_period & (o.flush_period - 1)))
         fail(NR_ERR_INVALID_ARG, "flush_period must be 0 or a power of two up to 64");
     for (int32_t s = 0; s < n_segs; ++s) {
@@ -281,10 +283,11 @@ int default_parts(int64_t L)
 }
 
 struct ClassKey {
-    int fp64, w, n, parts, method, flush;
+    int fp64, w, n, parts, method, flush, snap;
     bool operator<(const ClassKey& o) const
     {
-        return std::tie(fp64, w, n, parts, method, flush) < std::tie(o.fp64, o.w, o.n, o.parts, o.method, o.flush);
+        return std::tie(fp64, w, n, parts, method, flush, snap) <
+               std::tie(o.fp64, o.w, o.n, o.parts, o.method, o.flush, o.snap);
     }
 };
 
@@ -292,7 +295,7 @@ struct ClassKey {
 
 // Spreader configuration of one shape (precision, kernel width, grid, samples).
 struct Tuned {
-    int method, parts, flush;
+    int method, parts, flush, snap;
     double us_per_inst;
 };
 struct ShapeKey {
@@ -314,8 +317,8 @@ void load_tune_cache(const char* path)
     ShapeKey k;
     Tuned t;
     long long L;
-    while (std::fscanf(f, "%d %d %d %lld %d %d %d %lf", &k.fp64, &k.w, &k.n, &L, &t.method, &t.parts, &t.flush,
-                       &t.us_per_inst) == 8) {
+    while (std::fscanf(f, "%d %d %d %lld %d %d %d %d %lf", &k.fp64, &k.w, &k.n, &L, &t.method, &t.parts,
+                       &t.flush, &t.snap, &t.us_per_inst) == 9) {
         k.L = L;
         g_tuned[k] = t;
     }
@@ -329,8 +332,8 @@ void save_tune_cache(const char* path)
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
     for (auto& kv : g_tuned)
-        std::fprintf(f, "%d %d %d %lld %d %d %d %.6f\n", kv.first.fp64, kv.first.w, kv.first.n,
-                     (long long)kv.first.L, kv.second.method, kv.second.parts, kv.second.flush,
+        std::fprintf(f, "%d %d %d %lld %d %d %d %d %.6f\n", kv.first.fp64, kv.first.w, kv.first.n,
+                     (long long)kv.first.L, kv.second.method, kv.second.parts, kv.second.flush, kv.second.snap,
                      kv.second.us_per_inst);
     std::fclose(f);
     std::rename(tmp.c_str(), path);
@@ -455,7 +458,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     for (int32_t m = 0; m < n_tmpls; ++m) tmpl_beta[m] = chirp_beta(P.tmpls[m].mc_msun, P.tmpls[m].f0);
     // kernel width per distinct tolerance, and the last class looked up
     std::map<std::pair<double, int>, int> width_of;
-    ClassKey last_key{-1, -1, -1, -1, -1, -1};
+    ClassKey last_key{-1, -1, -1, -1, -1, -1, -1};
     size_t last_ci = 0;
     for (int64_t i = 0; i < N; ++i) {
         const nr_segment& g = P.segs[P.inst_seg[i]];
@@ -488,13 +491,15 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         int parts = o.parts ? o.parts : default_parts(g.n_samples);
         int method = (o.method == NR_METHOD_STAGED) ? NR_METHOD_STAGED : NR_METHOD_FUSED;
         int flush = o.flush_period;
+        int snap = o.moment_mode == 2 ? 1 : 0;
         if (o.tune) {
             const Tuned tu = tuned_config(o, g, t, tol_eff, fp64, w, n);
             parts = tu.parts;
             method = tu.method;
             flush = tu.flush;
+            snap = tu.snap;
         }
-        ClassKey key{fp64, w, n, parts, method, flush};
+        ClassKey key{fp64, w, n, parts, method, flush, snap};
         size_t ci;
         const bool same = !(key < last_key) && !(last_key < key);
         auto it = same ? class_of.end() : class_of.find(key);
@@ -512,6 +517,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             c->parts = parts;
             c->method = method;
             c->flush_period = flush;
+            c->snap = snap;
             c->beta_es = es_beta(w, sigma);
             P.classes.push_back(std::move(c));
         } else {
@@ -709,6 +715,7 @@ SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     a.w = c.w;
     a.parts = c.parts;
     a.flush_period = c.flush_period;
+    a.snap = c.snap;
     a.strain_complex = P.opt.strain_complex;
     return a;
 }
@@ -869,13 +876,15 @@ void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, vo
 
 // Time one spreader configuration on a synthetic batch of identical instances.
 double time_config(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
-                   int method, int parts, int flush, const void* strain, void* stat, int32_t* used, int64_t batch)
+                   int method, int parts, int flush, int snap, const void* strain, void* stat, int32_t* used,
+                   int64_t batch)
 {
     nr_options o2 = base;
     o2.tune = 0;
     o2.tune_cache = nullptr;
     o2.parts = parts;
     o2.flush_period = flush;
+    o2.moment_mode = snap ? 2 : 1;
     o2.method = method;
     o2.precision = fp64 ? NR_FP64 : NR_FP32;
     o2.profile = 0;
@@ -925,15 +934,17 @@ Tuned tune_shape(const nr_options& base, const nr_segment& g, const nr_template&
     stat.alloc((size_t)t.n_bins * 8, "tuning output");
     used.alloc(sizeof(int32_t), "tuning output");
     hip_check(hipMemset(stat.p, 0, (size_t)t.n_bins * 8), "tuning output");
-    Tuned best{NR_METHOD_FUSED, default_parts(L), 0, INFINITY};
+    Tuned best{NR_METHOD_FUSED, default_parts(L), 0, 0, INFINITY};
     for (int method : {NR_METHOD_FUSED, NR_METHOD_STAGED})
         for (int parts : {1, 2, 4}) {
             if (parts > 1 && L < (int64_t)kWave * parts * 16) continue;
-            for (int flush : {4, 16, 64}) {
-                const double us = time_config(base, g, t, tol, fp64, method, parts, flush, strain.p, stat.p,
-                                              (int32_t*)used.p, batch);
-                if (us < best.us_per_inst) best = Tuned{method, parts, flush, us};
-            }
+            for (int flush : {4, 16, 64})
+                for (int snap : {0, 1}) {
+                    if (snap && fp64) continue;  // cumulative snapshots are an FP32-class option
+                    const double us = time_config(base, g, t, tol, fp64, method, parts, flush, snap, strain.p,
+                                                  stat.p, (int32_t*)used.p, batch);
+                    if (us < best.us_per_inst) best = Tuned{method, parts, flush, snap, us};
+                }
         }
     return best;
 }
@@ -1081,6 +1092,7 @@ nr_status nufft_resample_query_class(nr_plan p, int32_t ci, nr_class_info* info)
     info->beta_es = c.beta_es;
     info->method = c.method;
     info->flush_period = c.flush_period;
+    info->snap = c.snap;
     info->n_inst = (int64_t)c.inst.size();
     info->n_points = c.n_points;
     for (const InstDev& d : c.inst) {

@@ -45,7 +45,7 @@ class NrOptions(ctypes.Structure):
                 ("parts", c_int32), ("profile", c_int32), ("use_graph", c_int32),
                 ("strain_length", c_int64), ("max_workspace_bytes", c_int64),
                 ("stream", c_void_p), ("tune_cache", c_char_p), ("tune", c_int32),
-                ("flush_period", c_int32)]
+                ("flush_period", c_int32), ("moment_mode", c_int32), ("reserved2", c_int32)]
 
 
 class NrPlanInfo(ctypes.Structure):
@@ -66,8 +66,8 @@ class NrClassInfo(ctypes.Structure):
     _fields_ = [("fp64", c_int32), ("w", c_int32), ("n", c_int32), ("degree", c_int32),
                 ("parts", c_int32), ("n_radix", c_int32), ("radix", c_int32 * 8),
                 ("beta_es", c_double), ("n_inst", c_int64), ("n_points", c_int64),
-                ("method", c_int32), ("flush_period", c_int32),
-                ("series_terms", c_int64), ("fallback_points", c_int64)]
+                ("method", c_int32), ("flush_period", c_int32), ("snap", c_int32),
+                ("reserved", c_int32), ("series_terms", c_int64), ("fallback_points", c_int64)]
 
 
 # symbol -> (restype, argtypes)
@@ -271,7 +271,7 @@ class Plan:
     def __init__(self, segs, tmpls, inst=None, tol=1e-6, precision="fp32", method="auto",
                  sigma=2.0, strict=False, parts=0, strain_complex=False, strain_length=0,
                  max_workspace_bytes=0, check_finite=False, profile=False, use_graph=False,
-                 tune=False, tune_cache=None, flush_period=0, stream=None):
+                 tune=False, tune_cache=None, flush_period=0, moment_mode=0, stream=None):
         import torch
         opt = nufft_resample_default_options()
         opt.precision = _PRECISION[precision]
@@ -287,6 +287,7 @@ class Plan:
         opt.use_graph = int(bool(use_graph))
         opt.tune = int(bool(tune))
         opt.flush_period = int(flush_period)
+        opt.moment_mode = int(moment_mode)
         self._tune_cache = tune_cache.encode() if tune_cache else None
         opt.tune_cache = self._tune_cache
         if stream is None and torch.cuda.is_available():

@@ -1,0 +1,88 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (fused FP32, tol 1e-6), on outputs the oracle computes one by one:
+sampled instances of the 1 h / 153,600-instance workload and segment sums of
+sampled templates, plus the full 512-instance ragged batch sampled."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_semicoherent_1h_sampled(gpu):
+    say("full-size 1 h workload, sampled")
+    import torch
+    from paper_2609_12476_amd import Plan, complex_view
+    w = synth.semicoherent(hours=1.0, n_mc=64, n_sub=20, seed=1).as_float32_strain()
+    with Plan.from_workload(w, tol=1e-6, precision="fp32", method="fused") as p:
+        assert p.info.n_inst == 153600
+        x = p.strain_tensor(w.strain, gpu)
+        sp, _, valid = p.execute(x, want=("spectra", "valid"))
+        stat, used = p.semicoherent_sum(x)
+        torch.cuda.synchronize()
+        X = complex_view(sp).cpu().numpy().astype(np.complex128)
+        ok = valid.cpu().numpy().astype(bool)
+        boff = p.bin_offsets()
+        S = stat.cpu().numpy().astype(np.float64)
+        U = used.cpu().numpy()
+        soff = p.stat_offsets()
+    rng = np.random.default_rng(17)
+    idx = np.sort(rng.choice(np.flatnonzero(ok), size=48, replace=False))
+    Xr, off, okr = oracle.spectra(w, inst_idx=idx)
+    assert okr.all()
+    errs = [rel(X[boff[i]:boff[i + 1]], Xr[off[j]:off[j + 1]]) for j, i in enumerate(idx)]
+    say(f"  spectra: max rel {max(errs):.2e}")
+    assert max(errs) <= 1e-5
+    # validity flags of every instance against the oracle's rule
+    s_all, m_all = w.instances()
+    for i in rng.choice(w.n_inst, size=2000, replace=False):
+        s, m = s_all[i], m_all[i]
+        assert ok[i] == oracle.valid(w.mc[m], w.f0[m], w.f_max[m], w.seg_t[s], w.seg_fs[s], w.seg_len[s])
+    # segment sums of sampled templates (all 120 segments each)
+    tm = np.sort(rng.choice(w.n_tmpl, size=8, replace=False))
+    sub = synth.Workload(**{**w.__dict__, "mc": w.mc[tm], "f0": w.f0[tm], "f_lo": w.f_lo[tm],
+                            "df": w.df[tm], "n_bins": w.n_bins[tm], "f_max": w.f_max[tm]})
+    Sr, soff_r, used_r = oracle.semicoherent(sub)
+    for q, m in enumerate(tm):
+        assert U[m] == used_r[q]
+        if used_r[q]:
+            e = rel(S[soff[m]:soff[m + 1]], Sr[soff_r[q]:soff_r[q + 1]])
+            assert e <= 1e-4, (m, e)
+
+
+def test_ragged_512_sampled(gpu):
+    say("full ragged batch, sampled")
+    import torch
+    from paper_2609_12476_amd import Plan, complex_view
+    w = synth.ragged_batch(n_inst=512, seed=2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with Plan.from_workload(w, precision="auto", use_graph=True, stream=s) as p:
+            x = p.strain_tensor(w.strain, gpu)
+            sp, _, valid = p.execute(x, want=("spectra", "valid"))
+            sp2, _, _ = p.execute(x, want=("spectra",))      # graph replay
+            s.synchronize()
+            assert torch.equal(sp, sp2)
+            X = complex_view(sp).cpu().numpy().astype(np.complex128)
+            ok = valid.cpu().numpy().astype(bool)
+            boff = p.bin_offsets()
+    rng = np.random.default_rng(19)
+    idx = np.sort(rng.choice(np.flatnonzero(ok), size=24, replace=False))
+    Xr, off, _ = oracle.spectra(w, inst_idx=idx)
+    for j, i in enumerate(idx):
+        t = w.inst_tol[i]
+        bound = max(t, 1e-5) if t >= 1e-6 else max(t, 1e-11)
+        assert rel(X[boff[i]:boff[i + 1]], Xr[off[j]:off[j + 1]]) <= bound, (i, t)
