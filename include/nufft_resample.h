@@ -116,7 +116,10 @@ typedef struct {
     int32_t strain_complex;     /* 0: real strain; 1: interleaved complex (re, im) */
     int32_t strict;             /* 1: unattainable tolerances are errors, not clamped */
     int32_t check_finite;       /* 1: execute scans the strain and synchronises */
-    int32_t parts;              /* waves per instance in the spreader; 0: automatic */
+    int32_t parts;              /* waves per instance in the spreader: 1, 2, 4, 8 or 16
+                                   (8 and 16 span 2 and 4 workgroups whose partial grids
+                                   the epilogue adds); 0: automatic (more waves per
+                                   instance when the plan is too small to fill the GPU) */
     int32_t profile;            /* 1: time every kernel launch with HIP events */
     int32_t use_graph;          /* 1: capture each call's launches in a HIP graph, keyed by
                                    its pointer arguments, and replay it on later calls with
@@ -148,7 +151,10 @@ typedef struct {
     int32_t n_classes;       /* kernel classes (precision, kernel width, grid size, parts) */
     int32_t out_fp64;        /* 1: outputs are double / complex double; 0: float */
     int32_t method;          /* nr_method of the first class (classes may differ when tuned) */
-    int32_t n_chunks;        /* launches per stage needed to cover the plan */
+    int32_t n_chunks;        /* spread launches per call: the chunks of every class, or,
+                                when every class fits one chunk and all grids fit the
+                                workspace together, the groups of classes that share a
+                                kernel and are launched together */
 } nr_plan_info;
 
 typedef struct {

@@ -40,10 +40,13 @@ struct InstDev {
 
 // One segment of a class: where its samples are and where its lane-major copy goes.
 struct SegDev {
+    void* dst;          // the class's lane-major strain buffer
     int64_t src_off;    // first sample in the caller's strain
     int64_t dst_off;    // first entry of the lane-major copy
     int32_t L;
     int32_t C;
+    int32_t parts;      // waves per instance of the class
+    int32_t pad_;
 };
 
 struct FftPlanDev {
@@ -60,50 +63,73 @@ struct SpreadArgs {
     const void* strain_lm;   // lane-major strain copy of the class (real or complex)
     const void* phase_table; // exp(2 pi i k / N), k < N (N = phase_table_size)
     void* points;            // staged point stream (chunk-relative)
-    void* grid;              // [chunk instances][n] complex
+    void* grid;              // [chunk instances][slots][n] complex
     int64_t first;           // first class instance of the chunk
     int64_t count;           // instances in the chunk
     int64_t pt_base;         // pt_off of the first instance of the chunk
     int32_t n;               // grid size
     int32_t w;               // kernel width
-    int32_t parts;           // waves per instance (1, 2 or 4)
+    int32_t parts;           // waves per instance (1, 2, 4, 8 or 16)
     int32_t flush_period;    // steps between collective flushes (power of two)
     int32_t strain_complex;
     int32_t snap;            // 1: cumulative moments with snapshots; 0: per-cell moments
 };
 
+// Workgroups of one launch of a class chunk, and grid slots per instance:
+// up to four waves of an instance share a workgroup; an instance with more
+// waves spans parts / 4 workgroups, each writing its own partial grid.
+__host__ __device__ inline int grid_slots(int parts) { return parts > 4 ? parts / 4 : 1; }
+__host__ __device__ inline int64_t spread_blocks(int64_t count, int parts)
+{
+    return parts > 4 ? count * (parts / 4) : (count * parts + 3) / 4;
+}
+
 struct EpilogueArgs {
     const InstDev* inst;
-    const void* grid;        // [chunk instances][n] complex
+    const void* grid;        // [chunk instances][slots][n] complex (partial grids are summed)
     const void* dec;         // [n] real deconvolution factors indexed by mode mod n
     const void* twiddle;     // [n] complex exp(-2 pi i t / n)
     FftPlanDev fft;
     int64_t first;
     int64_t count;
-    // spectra mode
-    void* spectra;           // complex output or null
-    void* power;             // real output or null
     // segment-sum mode
     const int32_t* tmpl_list;      // class instances of each class template, ascending
     const int64_t* tmpl_list_off;  // [n class templates + 1]
     const int64_t* tmpl_stat_off;  // stat offset of each class template
     const int32_t* tmpl_id;        // plan template id of each class template
-    const double* seg_weight;      // [n_segs] or null
-    void* stat;
-    int32_t* n_used;
     int32_t tmpl_first;            // class templates handled by this launch
     int32_t tmpl_count;
+    int32_t slots;                 // partial grids per instance
+    int32_t kmax;                  // largest K of the class (LDS sizing of the segment sum)
+};
+
+// Per-call pointers of the epilogue (the same for every class of a plan).
+struct EpilogueOut {
+    void* spectra;
+    void* power;
+    const double* seg_weight;
+    void* stat;
+    int32_t* n_used;
 };
 
 // Launch wrappers (defined in nr_kernels.hip).
-hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int32_t parts,
-                                    const void* strain, int strain_fp64, int strain_complex,
-                                    void* dst, int dst_fp64, hipStream_t st);
+hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, const void* strain,
+                                    int strain_fp64, int strain_complex, int dst_fp64, hipStream_t st);
+// One launch over several classes of the same kernel instantiation: tab
+// holds their arguments (device), block_off[ncls + 1] their first workgroup.
+hipError_t launch_spread_multi(const SpreadArgs* tab, const int64_t* block_off, int ncls,
+                               int64_t blocks, int fp64, int deg, int fused, int cplx, int snap,
+                               size_t lds, hipStream_t st);
+hipError_t launch_epilogue_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls,
+                                 int64_t blocks, int sum_mode, EpilogueOut out, int fp64,
+                                 int out_fp64, size_t lds, hipStream_t st);
+int64_t epilogue_blocks(const EpilogueArgs& a, int sum_mode);
 hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st);
 hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st);
-hipError_t launch_epilogue_spectra(const EpilogueArgs& a, int fp64, int out_fp64,
-                                   hipStream_t st);
-hipError_t launch_epilogue_sum(const EpilogueArgs& a, int fp64, int out_fp64, hipStream_t st);
+hipError_t launch_epilogue_spectra(const EpilogueArgs& a, const EpilogueOut& out, int fp64,
+                                   int out_fp64, hipStream_t st);
+hipError_t launch_epilogue_sum(const EpilogueArgs& a, const EpilogueOut& out, int fp64, int out_fp64,
+                               hipStream_t st);
 hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,
                                const int32_t* inst_K, int64_t n_inv, void* spectra,
                                void* power, int out_fp64, const uint8_t* mask, uint8_t* valid,

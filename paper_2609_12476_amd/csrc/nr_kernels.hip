@@ -164,9 +164,16 @@ __global__ __launch_bounds__(kBlock) void tau_kernel(SpreadArgs a)
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int parts = a.parts;
-    const int64_t item = (int64_t)blockIdx.x * (4 / parts) + wave / parts;
+    int64_t item;
+    int part;
+    if (parts <= 4) {
+        item = (int64_t)blockIdx.x * (4 / parts) + wave / parts;
+        part = wave % parts;
+    } else {
+        item = (int64_t)blockIdx.x / (parts / 4);
+        part = (int)((int64_t)blockIdx.x % (parts / 4)) * 4 + wave;
+    }
     if (item >= a.count) return;
-    const int part = wave % parts;
     const InstDev d = a.inst[a.first + item];
     TauConsts tc;
     load_tau(tc, d, a.coef, half_width_periods(a.w, a.n));
@@ -338,7 +345,7 @@ __device__ __forceinline__ void flush_diff(const Moments<T, D>& E, const Moments
 // Each wave owns its grid copy, so the LDS additions of one grid come from
 // one wave in program order and the result does not depend on scheduling.
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-__global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
+__device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock)
 {
     using P = typename PointOf<T>::type;
     constexpr int NT = 1 << PhaseTable<T>::bits;
@@ -356,9 +363,18 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
     for (int c = lane; c < n; c += kWave) grid[c] = cpx<T>{T(0), T(0)};
     __syncthreads();
 
-    const int per_block = 4 / parts;
-    const int64_t item = (int64_t)blockIdx.x * per_block + wave / parts;
-    const int part = wave % parts;
+    // waves of one instance inside this workgroup, which instance, which part
+    const int wpi = parts < 4 ? parts : 4;
+    int64_t item;
+    int part, slot = 0;
+    if (parts <= 4) {
+        item = lblock * (4 / parts) + wave / parts;
+        part = wave % parts;
+    } else {
+        item = lblock / (parts / 4);
+        slot = (int)(lblock % (parts / 4));
+        part = slot * 4 + wave;
+    }
     const T* __restrict__ A = reinterpret_cast<const T*>(a.taps);
 
     if (item < a.count) {
@@ -445,12 +461,13 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
     __syncthreads();
 
     if (item < a.count) {
-        // Sum the part grids of the instance in part order and store.
-        const int first_wave = (wave / parts) * parts;
-        cpx<T>* out = reinterpret_cast<cpx<T>*>(a.grid) + item * n;
-        for (int c = part * kWave + lane; c < n; c += kWave * parts) {
+        // Sum the grids of the instance's waves in this workgroup in wave
+        // order and store them as the workgroup's partial grid (slot).
+        const int first_wave = (wave / wpi) * wpi;
+        cpx<T>* out = reinterpret_cast<cpx<T>*>(a.grid) + (item * grid_slots(parts) + slot) * n;
+        for (int c = (wave % wpi) * kWave + lane; c < n; c += kWave * wpi) {
             T r = T(0), i = T(0);
-            for (int q = 0; q < parts; ++q) {
+            for (int q = 0; q < wpi; ++q) {
                 const cpx<T> gv = lds[(first_wave + q) * n + c];
                 r += gv.x;
                 i += gv.y;
@@ -458,6 +475,30 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
             out[c] = cpx<T>{r, i};
         }
     }
+}
+
+template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
+__global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
+{
+    spread_block<T, D, FUSED, CPLX, SNAP>(a, blockIdx.x);
+}
+
+// Class of workgroup b of a multi-class launch (block_off is ascending).
+__device__ __forceinline__ int class_of_block(const int64_t* __restrict__ block_off, int ncls, int64_t b)
+{
+    int c = 0;
+    while (c + 1 < ncls && block_off[c + 1] <= b) ++c;
+    return uniform(c);
+}
+
+template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
+__global__ __launch_bounds__(kBlock) void spread_multi_kernel(const SpreadArgs* __restrict__ tab,
+                                                              const int64_t* __restrict__ block_off,
+                                                              int ncls)
+{
+    const int c = class_of_block(block_off, ncls, blockIdx.x);
+    const SpreadArgs a = tab[c];
+    spread_block<T, D, FUSED, CPLX, SNAP>(a, (int64_t)blockIdx.x - block_off[c]);
 }
 
 // ------------------------------------------------------------------ FFT --
@@ -591,8 +632,26 @@ __device__ __forceinline__ cpx<T>* stage_twiddles(unsigned char* smem, const voi
     return tw;
 }
 
+// Load an instance's grid (sum of its partial grids, in slot order) into
+// the team's buffer.
+template <typename T>
+__device__ __forceinline__ void load_grid(const EpilogueArgs& a, int64_t local, cpx<T>* buf, int tid, int ts)
+{
+    const int n = a.fft.n;
+    const cpx<T>* g = reinterpret_cast<const cpx<T>*>(a.grid) + local * a.slots * n;
+    for (int c = tid; c < n; c += ts) {
+        cpx<T> v = g[c];
+        for (int q = 1; q < a.slots; ++q) {
+            const cpx<T> u = g[(int64_t)q * n + c];
+            v.x += u.x;
+            v.y += u.y;
+        }
+        buf[c] = v;
+    }
+}
+
 template <typename T, typename O>
-__global__ __launch_bounds__(kBlock) void epilogue_spectra_kernel(EpilogueArgs a)
+__device__ __forceinline__ void epilogue_spectra_block(const EpilogueArgs& a, const EpilogueOut& o, int64_t lblock)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.fft.n;
@@ -601,18 +660,16 @@ __global__ __launch_bounds__(kBlock) void epilogue_spectra_kernel(EpilogueArgs a
     const int nteam = kBlock / ts;
     const cpx<T>* tw = stage_twiddles<T>(smem_raw, a.twiddle, n);
     cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw) + n + (size_t)team * 2 * n;
-    const int64_t item = (int64_t)blockIdx.x * nteam + team;
+    const int64_t item = lblock * nteam + team;
     const bool live = item < a.count;
-    const cpx<T>* gsrc = reinterpret_cast<const cpx<T>*>(a.grid) + item * n;
-    if (live)
-        for (int c = tid; c < n; c += ts) buf[c] = gsrc[c];
+    if (live) load_grid<T>(a, item, buf, tid, ts);
     __syncthreads();
     const cpx<T>* res = fft_team<T>(buf, tw, a.fft, tid, ts);
     if (!live) return;
     const InstDev d = a.inst[a.first + item];
     const T* __restrict__ dec = reinterpret_cast<const T*>(a.dec);
-    cpx<O>* sp = reinterpret_cast<cpx<O>*>(a.spectra);
-    O* pw = reinterpret_cast<O*>(a.power);
+    cpx<O>* sp = reinterpret_cast<cpx<O>*>(o.spectra);
+    O* pw = reinterpret_cast<O*>(o.power);
     for (int k = tid; k < d.K; k += ts) {
         int l = k - d.m0;
         if (l < 0) l += n;
@@ -627,14 +684,15 @@ __global__ __launch_bounds__(kBlock) void epilogue_spectra_kernel(EpilogueArgs a
 // are shared round-robin by the teams, each team keeps FP64 partial sums,
 // and the partials are added in team order, so the result is reproducible.
 template <typename T, typename O>
-__global__ __launch_bounds__(kBlock) void epilogue_sum_kernel(EpilogueArgs a, int kmax)
+__device__ __forceinline__ void epilogue_sum_block(const EpilogueArgs& a, const EpilogueOut& o, int64_t lblock)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int n = a.fft.n;
+    const int kmax = a.kmax;
     const int ts = team_size_for(n);
     const int team = threadIdx.x / ts, tid = threadIdx.x % ts;
     const int nteam = kBlock / ts;
-    const int ct = a.tmpl_first + blockIdx.x;
+    const int ct = a.tmpl_first + (int)lblock;
     int64_t lo = a.tmpl_list_off[ct], hi = a.tmpl_list_off[ct + 1];
     // entries of this chunk: class instances in [first, first + count)
     {
@@ -670,14 +728,13 @@ __global__ __launch_bounds__(kBlock) void epilogue_sum_kernel(EpilogueArgs a, in
         int ci = 0;
         if (live) {
             ci = a.tmpl_list[e];
-            const cpx<T>* gsrc = reinterpret_cast<const cpx<T>*>(a.grid) + (int64_t)(ci - a.first) * n;
-            for (int c = tid; c < n; c += ts) buf[c] = gsrc[c];
+            load_grid<T>(a, ci - a.first, buf, tid, ts);
         }
         __syncthreads();
         const cpx<T>* res = fft_team<T>(buf, tw, a.fft, tid, ts);
         if (live) {
             const InstDev d = a.inst[ci];
-            const double wgt = a.seg_weight ? a.seg_weight[d.seg] : 1.0;
+            const double wgt = o.seg_weight ? o.seg_weight[d.seg] : 1.0;
             for (int k = tid; k < K; k += ts) {
                 int l = k - d.m0;
                 if (l < 0) l += n;
@@ -688,42 +745,65 @@ __global__ __launch_bounds__(kBlock) void epilogue_sum_kernel(EpilogueArgs a, in
         }
         __syncthreads();
     }
-    O* stat = reinterpret_cast<O*>(a.stat) + a.tmpl_stat_off[ct];
+    O* stat = reinterpret_cast<O*>(o.stat) + a.tmpl_stat_off[ct];
     for (int k = threadIdx.x; k < K; k += kBlock) {
         double s = 0.0;
         for (int t = 0; t < nteam; ++t) s += part[(size_t)t * kmax + k];
         stat[k] = (O)((double)stat[k] + s);
     }
-    if (threadIdx.x == 0 && a.n_used) a.n_used[a.tmpl_id[ct]] += (int32_t)cnt;
+    if (threadIdx.x == 0 && o.n_used) o.n_used[a.tmpl_id[ct]] += (int32_t)cnt;
+}
+
+template <typename T, typename O, int SUM>
+__global__ __launch_bounds__(kBlock) void epilogue_kernel(EpilogueArgs a, EpilogueOut o)
+{
+    if (SUM)
+        epilogue_sum_block<T, O>(a, o, blockIdx.x);
+    else
+        epilogue_spectra_block<T, O>(a, o, blockIdx.x);
+}
+
+template <typename T, typename O, int SUM>
+__global__ __launch_bounds__(kBlock) void epilogue_multi_kernel(const EpilogueArgs* __restrict__ tab,
+                                                                const int64_t* __restrict__ block_off,
+                                                                int ncls, EpilogueOut o)
+{
+    const int c = class_of_block(block_off, ncls, blockIdx.x);
+    const EpilogueArgs a = tab[c];
+    const int64_t lb = (int64_t)blockIdx.x - block_off[c];
+    if (SUM)
+        epilogue_sum_block<T, O>(a, o, lb);
+    else
+        epilogue_spectra_block<T, O>(a, o, lb);
 }
 
 // ------------------------------------------------------------ utilities --
 
+// One workgroup per class segment: every part's rows of its lane-major copy.
 template <typename Ti, typename To>
 __global__ __launch_bounds__(kBlock) void strain_lane_major_kernel(const SegDev* __restrict__ segs,
-                                                                   int32_t parts,
-                                                                   const Ti* __restrict__ src,
-                                                                   To* __restrict__ dst, int cplx)
+                                                                   const Ti* __restrict__ src, int cplx)
 {
-    const int item = blockIdx.x;
-    const SegDev sd = segs[item / parts];
-    const int part = item % parts;
+    const SegDev sd = segs[blockIdx.x];
+    To* __restrict__ dst = reinterpret_cast<To*>(sd.dst);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t v = (int64_t)part * kWave + lane;
-    const int64_t row0 = sd.dst_off + (int64_t)part * sd.C * kWave + lane;
-    for (int s = wave; s < sd.C; s += 4) {
-        const int64_t j = v * sd.C + s;
-        const int64_t o = row0 + (int64_t)s * kWave;
-        if (cplx) {
-            To re = To(0), im = To(0);
-            if (j < sd.L) {
-                re = (To)src[2 * (sd.src_off + j)];
-                im = (To)src[2 * (sd.src_off + j) + 1];
+    for (int part = 0; part < sd.parts; ++part) {
+        const int64_t v = (int64_t)part * kWave + lane;
+        const int64_t row0 = sd.dst_off + (int64_t)part * sd.C * kWave + lane;
+        for (int s = wave; s < sd.C; s += 4) {
+            const int64_t j = v * sd.C + s;
+            const int64_t o = row0 + (int64_t)s * kWave;
+            if (cplx) {
+                To re = To(0), im = To(0);
+                if (j < sd.L) {
+                    re = (To)src[2 * (sd.src_off + j)];
+                    im = (To)src[2 * (sd.src_off + j) + 1];
+                }
+                dst[2 * o] = re;
+                dst[2 * o + 1] = im;
+            } else {
+                dst[o] = (j < sd.L) ? (To)src[sd.src_off + j] : To(0);
             }
-            dst[2 * o] = re;
-            dst[2 * o + 1] = im;
-        } else {
-            dst[o] = (j < sd.L) ? (To)src[sd.src_off + j] : To(0);
         }
     }
 }
@@ -787,32 +867,26 @@ size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode)
     return b;
 }
 
-hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int32_t parts,
-                                    const void* strain, int strain_fp64, int strain_complex,
-                                    void* dst, int dst_fp64, hipStream_t st)
+hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, const void* strain,
+                                    int strain_fp64, int strain_complex, int dst_fp64, hipStream_t st)
 {
     if (n_segs <= 0) return hipSuccess;
-    dim3 grid((unsigned)(n_segs * parts)), block(kBlock);
+    dim3 grid((unsigned)n_segs), block(kBlock);
     if (strain_fp64 && dst_fp64)
-        strain_lane_major_kernel<double, double><<<grid, block, 0, st>>>(
-            segs, parts, (const double*)strain, (double*)dst, strain_complex);
+        strain_lane_major_kernel<double, double><<<grid, block, 0, st>>>(segs, (const double*)strain, strain_complex);
     else if (strain_fp64)
-        strain_lane_major_kernel<double, float><<<grid, block, 0, st>>>(
-            segs, parts, (const double*)strain, (float*)dst, strain_complex);
+        strain_lane_major_kernel<double, float><<<grid, block, 0, st>>>(segs, (const double*)strain, strain_complex);
     else if (dst_fp64)
-        strain_lane_major_kernel<float, double><<<grid, block, 0, st>>>(
-            segs, parts, (const float*)strain, (double*)dst, strain_complex);
+        strain_lane_major_kernel<float, double><<<grid, block, 0, st>>>(segs, (const float*)strain, strain_complex);
     else
-        strain_lane_major_kernel<float, float><<<grid, block, 0, st>>>(
-            segs, parts, (const float*)strain, (float*)dst, strain_complex);
+        strain_lane_major_kernel<float, float><<<grid, block, 0, st>>>(segs, (const float*)strain, strain_complex);
     return hipGetLastError();
 }
 
 hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st)
 {
     if (a.count <= 0) return hipSuccess;
-    const int64_t per_block = 4 / a.parts;
-    dim3 grid((unsigned)((a.count + per_block - 1) / per_block)), block(kBlock);
+    dim3 grid((unsigned)spread_blocks(a.count, a.parts)), block(kBlock);
     if (fp64)
         tau_kernel<double><<<grid, block, 0, st>>>(a);
     else
@@ -827,39 +901,56 @@ static void launch_spread_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStrea
     spread_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(a);
 }
 
-template <typename T, int D, bool SNAP>
-static void launch_spread_s(const SpreadArgs& a, int fused, dim3 grid, size_t lds, hipStream_t st)
+// Arguments of a multi-class launch (the same kernel instantiation).
+struct MultiSpread {
+    const SpreadArgs* tab;
+    const int64_t* block_off;
+    int ncls;
+};
+
+template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
+static void launch_spread_k(const MultiSpread& m, dim3 grid, size_t lds, hipStream_t st)
+{
+    allow_lds(spread_multi_kernel<T, D, FUSED, CPLX, SNAP>, lds);
+    spread_multi_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(m.tab, m.block_off, m.ncls);
+}
+
+template <typename T, int D, bool SNAP, typename A>
+static void launch_spread_s(const A& a, int fused, int cplx, dim3 grid, size_t lds, hipStream_t st)
 {
     if (fused) {
-        if (a.strain_complex) launch_spread_k<T, D, true, true, SNAP>(a, grid, lds, st);
+        if (cplx) launch_spread_k<T, D, true, true, SNAP>(a, grid, lds, st);
         else launch_spread_k<T, D, true, false, SNAP>(a, grid, lds, st);
     } else {
-        if (a.strain_complex) launch_spread_k<T, D, false, true, SNAP>(a, grid, lds, st);
+        if (cplx) launch_spread_k<T, D, false, true, SNAP>(a, grid, lds, st);
         else launch_spread_k<T, D, false, false, SNAP>(a, grid, lds, st);
     }
 }
 
+// cumulative snapshots need a third register set: FP32 classes of moderate degree only
 template <typename T, int D>
-static hipError_t launch_spread_d(const SpreadArgs& a, int fused, hipStream_t st)
+constexpr bool snap_allowed() { return sizeof(T) == 4 && D <= 12; }
+
+template <typename T, int D, typename A>
+static hipError_t launch_spread_d(const A& a, int fused, int cplx, int snap, int64_t blocks, size_t lds,
+                                  hipStream_t st)
 {
-    const int64_t per_block = 4 / a.parts;
-    dim3 grid((unsigned)((a.count + per_block - 1) / per_block));
-    const size_t lds = spread_lds_bytes(sizeof(T) == 8, a.n);
-    // cumulative snapshots need a third register set: FP32 classes of moderate degree only
-    constexpr bool snap_ok = sizeof(T) == 4 && D <= 12;
-    if (snap_ok && a.snap)
-        launch_spread_s<T, D, snap_ok>(a, fused, grid, lds, st);
+    dim3 grid((unsigned)blocks);
+    constexpr bool snap_ok = snap_allowed<T, D>();
+    if (snap_ok && snap)
+        launch_spread_s<T, D, snap_ok>(a, fused, cplx, grid, lds, st);
     else
-        launch_spread_s<T, D, false>(a, fused, grid, lds, st);
+        launch_spread_s<T, D, false>(a, fused, cplx, grid, lds, st);
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_spread_t(const SpreadArgs& a, int deg, int fused, hipStream_t st)
+template <typename T, typename A>
+static hipError_t launch_spread_t(const A& a, int deg, int fused, int cplx, int snap, int64_t blocks,
+                                  size_t lds, hipStream_t st)
 {
     switch (deg) {
 #define NR_CASE(DD) \
-    case DD: return launch_spread_d<T, DD>(a, fused, st);
+    case DD: return launch_spread_d<T, DD>(a, fused, cplx, snap, blocks, lds, st);
         NR_CASE(2) NR_CASE(3) NR_CASE(4) NR_CASE(5) NR_CASE(6) NR_CASE(7) NR_CASE(8) NR_CASE(9)
         NR_CASE(10) NR_CASE(11) NR_CASE(12) NR_CASE(13) NR_CASE(14) NR_CASE(15) NR_CASE(16)
         NR_CASE(17) NR_CASE(18)
@@ -871,47 +962,80 @@ static hipError_t launch_spread_t(const SpreadArgs& a, int deg, int fused, hipSt
 hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st)
 {
     if (a.count <= 0) return hipSuccess;
-    return fp64 ? launch_spread_t<double>(a, deg, fused, st)
-                : launch_spread_t<float>(a, deg, fused, st);
+    const int64_t blocks = spread_blocks(a.count, a.parts);
+    const size_t lds = spread_lds_bytes(fp64, a.n);
+    return fp64 ? launch_spread_t<double>(a, deg, fused, a.strain_complex, a.snap, blocks, lds, st)
+                : launch_spread_t<float>(a, deg, fused, a.strain_complex, a.snap, blocks, lds, st);
 }
 
-hipError_t launch_epilogue_spectra(const EpilogueArgs& a, int fp64, int out_fp64, hipStream_t st)
+hipError_t launch_spread_multi(const SpreadArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
+                               int fp64, int deg, int fused, int cplx, int snap, size_t lds, hipStream_t st)
 {
-    if (a.count <= 0) return hipSuccess;
-    const int n = a.fft.n;
-    const int nteam = kBlock / team_size_for(n);
-    dim3 grid((unsigned)((a.count + nteam - 1) / nteam)), block(kBlock);
-    const size_t lds = epilogue_lds_bytes(fp64, n, 0, 0);
-    if (fp64) {
-        allow_lds(epilogue_spectra_kernel<double, double>, lds);
-        epilogue_spectra_kernel<double, double><<<grid, block, lds, st>>>(a);
-    } else if (out_fp64) {
-        allow_lds(epilogue_spectra_kernel<float, double>, lds);
-        epilogue_spectra_kernel<float, double><<<grid, block, lds, st>>>(a);
-    } else {
-        allow_lds(epilogue_spectra_kernel<float, float>, lds);
-        epilogue_spectra_kernel<float, float><<<grid, block, lds, st>>>(a);
-    }
+    if (blocks <= 0) return hipSuccess;
+    const MultiSpread m{tab, block_off, ncls};
+    return fp64 ? launch_spread_t<double>(m, deg, fused, cplx, snap, blocks, lds, st)
+                : launch_spread_t<float>(m, deg, fused, cplx, snap, blocks, lds, st);
+}
+
+int64_t epilogue_blocks(const EpilogueArgs& a, int sum_mode)
+{
+    if (sum_mode) return a.tmpl_count;
+    const int nteam = kBlock / team_size_for(a.fft.n);
+    return (a.count + nteam - 1) / nteam;
+}
+
+template <typename T, typename O, int SUM>
+static hipError_t launch_epi_k(const EpilogueArgs& a, const EpilogueOut& o, int64_t blocks, size_t lds,
+                               hipStream_t st)
+{
+    allow_lds(epilogue_kernel<T, O, SUM>, lds);
+    epilogue_kernel<T, O, SUM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(a, o);
     return hipGetLastError();
 }
 
-hipError_t launch_epilogue_sum(const EpilogueArgs& a, int fp64, int out_fp64, hipStream_t st)
+template <typename T, typename O, int SUM>
+static hipError_t launch_epi_multi_k(const EpilogueArgs* tab, const int64_t* off, int ncls, const EpilogueOut& o,
+                                     int64_t blocks, size_t lds, hipStream_t st)
 {
-    if (a.count <= 0 || a.tmpl_count <= 0) return hipSuccess;
-    dim3 grid((unsigned)a.tmpl_count), block(kBlock);
-    const int kmax = a.fft.n;  // K <= n for every instance of a class
-    const size_t lds = epilogue_lds_bytes(fp64, a.fft.n, kmax, 1);
-    if (fp64) {
-        allow_lds(epilogue_sum_kernel<double, double>, lds);
-        epilogue_sum_kernel<double, double><<<grid, block, lds, st>>>(a, kmax);
-    } else if (out_fp64) {
-        allow_lds(epilogue_sum_kernel<float, double>, lds);
-        epilogue_sum_kernel<float, double><<<grid, block, lds, st>>>(a, kmax);
-    } else {
-        allow_lds(epilogue_sum_kernel<float, float>, lds);
-        epilogue_sum_kernel<float, float><<<grid, block, lds, st>>>(a, kmax);
-    }
+    allow_lds(epilogue_multi_kernel<T, O, SUM>, lds);
+    epilogue_multi_kernel<T, O, SUM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(tab, off, ncls, o);
     return hipGetLastError();
+}
+
+template <int SUM>
+static hipError_t launch_epi(const EpilogueArgs& a, const EpilogueOut& o, int fp64, int out_fp64, hipStream_t st)
+{
+    const int64_t blocks = epilogue_blocks(a, SUM);
+    if (blocks <= 0 || a.count <= 0) return hipSuccess;
+    const size_t lds = epilogue_lds_bytes(fp64, a.fft.n, a.kmax, SUM);
+    if (fp64) return launch_epi_k<double, double, SUM>(a, o, blocks, lds, st);
+    if (out_fp64) return launch_epi_k<float, double, SUM>(a, o, blocks, lds, st);
+    return launch_epi_k<float, float, SUM>(a, o, blocks, lds, st);
+}
+
+hipError_t launch_epilogue_spectra(const EpilogueArgs& a, const EpilogueOut& o, int fp64, int out_fp64,
+                                   hipStream_t st)
+{
+    return launch_epi<0>(a, o, fp64, out_fp64, st);
+}
+
+hipError_t launch_epilogue_sum(const EpilogueArgs& a, const EpilogueOut& o, int fp64, int out_fp64, hipStream_t st)
+{
+    return launch_epi<1>(a, o, fp64, out_fp64, st);
+}
+
+hipError_t launch_epilogue_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
+                                 int sum_mode, EpilogueOut o, int fp64, int out_fp64, size_t lds, hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    if (sum_mode) {
+        if (fp64) return launch_epi_multi_k<double, double, 1>(tab, block_off, ncls, o, blocks, lds, st);
+        if (out_fp64) return launch_epi_multi_k<float, double, 1>(tab, block_off, ncls, o, blocks, lds, st);
+        return launch_epi_multi_k<float, float, 1>(tab, block_off, ncls, o, blocks, lds, st);
+    }
+    if (fp64) return launch_epi_multi_k<double, double, 0>(tab, block_off, ncls, o, blocks, lds, st);
+    if (out_fp64) return launch_epi_multi_k<float, double, 0>(tab, block_off, ncls, o, blocks, lds, st);
+    return launch_epi_multi_k<float, float, 0>(tab, block_off, ncls, o, blocks, lds, st);
 }
 
 hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -46,6 +47,11 @@ struct DevBuf {
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes)
+    {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
     ~DevBuf()
     {
         if (p) (void)hipFree(p);
@@ -78,21 +84,35 @@ struct Class {
     int fp64, w, n, deg, parts;
     int method = NR_METHOD_FUSED;
     int snap = 0;
+    int kmax = 0;                      // largest K of the class
+    int64_t grid_off = 0;              // batched mode: the class's grids and point stream
+    int64_t pts_off = 0;               //   inside the plan's buffers (bytes)
     double beta_es;
     std::vector<int> radix;
     std::vector<InstDev> inst;         // class instances, ascending plan index
     std::vector<double> coef;          // Horner coefficients
-    std::vector<SegDev> segs;          // lane-major strain layout
+    std::vector<SegDev> segs;          // lane-major strain layout (dst set once allocated)
     int64_t strain_entries = 0;        // lane-major entries (complex counts once)
     int64_t n_points = 0;              // sum of L
+    int64_t pt_entries = 0;            // point-stream entries (runs padded to C samples)
     std::vector<Chunk> chunks;
     // segment-sum bookkeeping
     std::vector<int32_t> tmpl_id, tmpl_list;
     std::vector<int64_t> tmpl_list_off, tmpl_stat_off;
     // device copies
     int flush_period = 16;
-    DevBuf d_inst, d_coef, d_taps, d_dec, d_tw, d_phase, d_segs, d_strain, d_tmpl_id, d_tmpl_list,
+    DevBuf d_inst, d_coef, d_taps, d_dec, d_tw, d_phase, d_strain, d_tmpl_id, d_tmpl_list,
         d_tmpl_list_off, d_tmpl_stat_off;
+};
+
+// Classes launched together: one kernel instantiation and one LDS
+// occupancy tier, each class's arguments in a device table.
+struct Group {
+    std::vector<int> cls;
+    int fp64 = 0, deg = 0, fused = 1, snap = 0;
+    size_t lds[2] = {0, 0};            // spread: [0]; epilogue: [0] spectra, [1] segment sum
+    int64_t blocks[2] = {0, 0};
+    DevBuf d_tab, d_off[2];
 };
 
 }  // namespace
@@ -112,6 +132,13 @@ struct nr_plan_s {
     int out_fp64 = 0, strain_fp64 = 0, method = NR_METHOD_FUSED;
     int64_t n_valid = 0, valid_points = 0;
     DevBuf d_points, d_grid, d_mask, d_bin_off, d_inst_K, d_invalid, d_flag;
+    // lane-major layout of every class, by destination precision
+    std::vector<SegDev> lm_segs[2];
+    DevBuf d_lm_segs[2];
+    // batched mode: every class in one chunk with its own grid region, the
+    // classes launched in groups instead of one after another
+    bool batched = false;
+    std::vector<Group> spread_groups, epi_groups;
     int64_t n_invalid = 0;
     int64_t workspace = 0;
     int n_chunks = 0;
@@ -156,8 +183,8 @@ void validate(const nr_segment* segs, int32_t n_segs, const nr_template* tmpls, 
     if (o.method < NR_METHOD_AUTO || o.method > NR_METHOD_FUSED) fail(NR_ERR_INVALID_ARG, "unknown method");
     if (o.sigma > 0.0 && !(o.sigma >= 1.25 && o.sigma <= 4.0))
         fail(NR_ERR_INVALID_ARG, "sigma must be in [1.25, 4]");
-    if (o.parts != 0 && o.parts != 1 && o.parts != 2 && o.parts != 4)
-        fail(NR_ERR_INVALID_ARG, "parts must be 0, 1, 2 or 4");
+    if (o.parts != 0 && o.parts != 1 && o.parts != 2 && o.parts != 4 && o.parts != 8 && o.parts != 16)
+        fail(NR_ERR_INVALID_ARG, "parts must be 0, 1, 2, 4, 8 or 16");
     if (o.strain_length < 0 || o.max_workspace_bytes < 0) fail(NR_ERR_INVALID_ARG, "negative size option");
     if (o.moment_mode < 0 || o.moment_mode > 2) fail(NR_ERR_INVALID_ARG, "moment_mode must be 0, 1 or 2");
     if (o.flush_period < 0 || o.flush_period > 64 || (o.flush_period & (o.flush_period - 1)))
@@ -282,6 +309,15 @@ int default_parts(int64_t L)
     return 4;
 }
 
+// Waves per instance when the whole plan has too few waves to fill the chip:
+// enough to bring the samples per lane down to about 64 (at most 16 waves).
+int small_plan_parts(int64_t L)
+{
+    int p = default_parts(L);
+    while (p < 16 && (L + (int64_t)kWave * p - 1) / ((int64_t)kWave * p) > 64) p *= 2;
+    return p;
+}
+
 struct ClassKey {
     int fp64, w, n, parts, method, flush, snap;
     bool operator<(const ClassKey& o) const
@@ -389,6 +425,7 @@ void build_class_tables(Class& c, double tol_cls, double sigma)
 
 Tuned tuned_config(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
                    int w, int n);
+void build_groups(nr_plan_s& P);
 
 void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_template* tmpls,
                  int32_t n_tmpls, const nr_instance* inst, int64_t n_inst, double tol)
@@ -454,6 +491,13 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         }
         n_max_of[f] = lo;
     }
+    // plans with few waves: spread each instance over more waves
+    bool small_plan = false;
+    if (o.parts == 0) {
+        int64_t waves = 0;
+        for (int64_t i = 0; i < N && waves < 16384; ++i) waves += default_parts(P.segs[P.inst_seg[i]].n_samples);
+        small_plan = waves < 16384;
+    }
     std::vector<double> tmpl_beta(n_tmpls);
     for (int32_t m = 0; m < n_tmpls; ++m) tmpl_beta[m] = chirp_beta(P.tmpls[m].mc_msun, P.tmpls[m].f0);
     // kernel width per distinct tolerance, and the last class looked up
@@ -488,7 +532,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": grid size " + std::to_string(n) +
                                          " exceeds the supported maximum " + std::to_string(n_max) +
                                          " (lower n_bins or sigma)");
-        int parts = o.parts ? o.parts : default_parts(g.n_samples);
+        int parts = o.parts ? o.parts : small_plan ? small_plan_parts(g.n_samples) : default_parts(g.n_samples);
         int method = (o.method == NR_METHOD_STAGED) ? NR_METHOD_STAGED : NR_METHOD_FUSED;
         int flush = o.flush_period;
         int snap = o.moment_mode == 2 ? 1 : 0;
@@ -549,13 +593,14 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             if (d.ndeg < 0) d.coef_off = 0;
         }
         c.inst.push_back(d);
+        c.kmax = std::max(c.kmax, K);
         c.n_points += g.n_samples;
     }
     for (auto& kv : class_of) build_class_tables(*P.classes[kv.second], class_tol[kv.first], sigma);
 
     // Lane-major strain layout per class, point-stream offsets, templates
     const size_t psize_f = 8, psize_d = 16;
-    int64_t grid_chunk_bytes = 0, point_chunk_bytes = 0;
+    int64_t grid_chunk_bytes = 0, point_chunk_bytes = 0, grid_total = 0, point_total = 0;
     const int64_t cap = o.max_workspace_bytes > 0 ? o.max_workspace_bytes : (int64_t(8) << 30);
     int64_t fixed_bytes = 0;
     for (auto& cp : P.classes) {
@@ -573,6 +618,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
                 sd.dst_off = c.strain_entries;
                 sd.L = d.L;
                 sd.C = d.C;
+                sd.parts = c.parts;
                 c.segs.push_back(sd);
                 seg_at[d.seg] = sd.dst_off;
                 c.strain_entries += (int64_t)c.parts * d.C * kWave;
@@ -590,6 +636,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             }
             lists[tmpl_at[pm]].push_back((int32_t)k);
         }
+        c.pt_entries = pt;
         c.tmpl_list_off.push_back(0);
         for (auto& l : lists) {
             c.tmpl_list.insert(c.tmpl_list.end(), l.begin(), l.end());
@@ -613,7 +660,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             for (int32_t k : lists[t]) ct_of[k] = (int32_t)t;
         fixed_bytes += c.strain_entries * esize;
         // chunks bounded by the workspace cap
-        const int64_t gsize = (int64_t)c.n * (c.fp64 ? 16 : 8);
+        const int64_t gsize = (int64_t)c.n * (c.fp64 ? 16 : 8) * grid_slots(c.parts);
         const int64_t psz = c.method == NR_METHOD_STAGED ? (c.fp64 ? psize_d : psize_f) : 0;
         const int64_t budget = std::max<int64_t>(cap / 2, 1);
         int64_t k0 = 0;
@@ -633,6 +680,8 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             c.chunks.push_back(ch);
             grid_chunk_bytes = std::max(grid_chunk_bytes, gb);
             point_chunk_bytes = std::max(point_chunk_bytes, pb);
+            grid_total += gb;
+            point_total += pb;
             k0 = k1;
         }
         P.n_chunks += (int)c.chunks.size();
@@ -640,21 +689,50 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         c.d_inst.upload(c.inst, "instances");
         c.coef.resize(c.coef.size() + kHornerPad, 0.0);  // whole-width register loads stay in bounds
         c.d_coef.upload(c.coef, "tau series");
-        c.d_segs.upload(c.segs, "segments");
         c.d_strain.alloc((size_t)c.strain_entries * esize, "lane-major strain");
+        for (SegDev& sd : c.segs) {
+            sd.dst = c.d_strain.p;
+            P.lm_segs[c.fp64].push_back(sd);
+        }
         c.d_tmpl_id.upload(c.tmpl_id, "templates");
         c.d_tmpl_list.upload(c.tmpl_list, "template lists");
         c.d_tmpl_list_off.upload(c.tmpl_list_off, "template lists");
         c.d_tmpl_stat_off.upload(c.tmpl_stat_off, "template offsets");
-        P.workspace += (int64_t)(c.d_inst.bytes + c.d_coef.bytes + c.d_segs.bytes + c.d_strain.bytes +
+        P.workspace += (int64_t)(c.d_inst.bytes + c.d_coef.bytes + c.d_strain.bytes +
                                  c.d_phase.bytes + c.d_taps.bytes + c.d_dec.bytes + c.d_tw.bytes + c.d_tmpl_id.bytes +
                                  c.d_tmpl_list.bytes + c.d_tmpl_list_off.bytes + c.d_tmpl_stat_off.bytes);
     }
     if (fixed_bytes + grid_chunk_bytes + point_chunk_bytes > cap)
         fail(NR_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(fixed_bytes + grid_chunk_bytes + point_chunk_bytes) +
                                        " bytes exceeds max_workspace_bytes " + std::to_string(cap));
+    // Batched mode when every class fits one chunk and all grids fit together.
+    bool one_chunk = true;
+    for (auto& cp : P.classes) one_chunk = one_chunk && cp->chunks.size() <= 1;
+    P.batched = P.classes.size() > 1 && one_chunk && fixed_bytes + grid_total + point_total <= cap &&
+                grid_total + point_total <= std::max<int64_t>(cap / 2, 1);
+    if (P.batched) {
+        int64_t go = 0, po = 0;
+        for (auto& cp : P.classes) {
+            Class& c = *cp;
+            c.grid_off = go;
+            c.pts_off = po;
+            const int64_t gsize = (int64_t)c.n * (c.fp64 ? 16 : 8) * grid_slots(c.parts);
+            go += (int64_t)c.inst.size() * gsize;
+            if (c.method == NR_METHOD_STAGED)
+                po += c.pt_entries * (c.fp64 ? (int64_t)psize_d : (int64_t)psize_f);
+            go = (go + 255) & ~int64_t(255);
+            po = (po + 255) & ~int64_t(255);
+        }
+        grid_chunk_bytes = go;
+        point_chunk_bytes = po;
+    }
     P.d_grid.alloc((size_t)grid_chunk_bytes, "grid");
     if (point_chunk_bytes > 0) P.d_points.alloc((size_t)point_chunk_bytes, "point stream");
+    for (int f = 0; f < 2; ++f) P.d_lm_segs[f].upload(P.lm_segs[f], "segments");
+    if (P.batched) {
+        build_groups(P);
+        P.n_chunks = (int)P.spread_groups.size();
+    }
     if (!P.classes.empty()) P.method = P.classes[0]->method;
     P.d_mask.upload(P.valid, "mask");
     std::vector<int32_t> invalid;
@@ -666,6 +744,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     P.d_inst_K.upload(P.inst_K, "bins");
     P.d_flag.alloc(sizeof(int32_t), "flag");
     P.workspace += (int64_t)(P.d_grid.bytes + P.d_points.bytes + P.d_mask.bytes + P.d_invalid.bytes +
+                             P.d_lm_segs[0].bytes + P.d_lm_segs[1].bytes +
                              P.d_bin_off.bytes + P.d_inst_K.bytes + P.d_flag.bytes);
 }
 
@@ -706,8 +785,8 @@ SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     a.taps = c.d_taps.p;
     a.strain_lm = c.d_strain.p;
     a.phase_table = c.d_phase.p;
-    a.points = P.d_points.p;
-    a.grid = P.d_grid.p;
+    a.points = (char*)P.d_points.p + c.pts_off;
+    a.grid = (char*)P.d_grid.p + c.grid_off;
     a.first = ch.first;
     a.count = ch.count;
     a.pt_base = ch.pt_base;
@@ -724,7 +803,7 @@ EpilogueArgs epilogue_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
 {
     EpilogueArgs e{};
     e.inst = (const InstDev*)c.d_inst.p;
-    e.grid = P.d_grid.p;
+    e.grid = (const char*)P.d_grid.p + c.grid_off;
     e.dec = c.d_dec.p;
     e.twiddle = c.d_tw.p;
     e.fft.n = c.n;
@@ -738,7 +817,99 @@ EpilogueArgs epilogue_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     e.tmpl_id = (const int32_t*)c.d_tmpl_id.p;
     e.tmpl_first = ch.tmpl_first;
     e.tmpl_count = ch.tmpl_count;
+    e.slots = grid_slots(c.parts);
+    e.kmax = c.kmax;
     return e;
+}
+
+// LDS occupancy tier: workgroups per compute unit that the LDS allows.
+int lds_tier(size_t bytes)
+{
+    return (int)std::min<size_t>(8, kLdsBytes / std::max<size_t>(bytes, 1));
+}
+
+void build_groups(nr_plan_s& P)
+{
+    // spread: same kernel instantiation and LDS tier
+    std::map<std::array<int, 5>, size_t> sg;
+    // epilogue groups: a segment sum adds into its templates' statistics
+    // without atomics, so the classes of one group have disjoint templates
+    std::map<std::array<int, 2>, std::vector<size_t>> eg;
+    std::vector<std::vector<char>> eg_tmpls;
+    for (size_t ci = 0; ci < P.classes.size(); ++ci) {
+        const Class& c = *P.classes[ci];
+        if (c.inst.empty()) continue;
+        const int fused = c.method == NR_METHOD_FUSED;
+        const int snap = (c.snap && !c.fp64 && c.deg <= 12) ? 1 : 0;
+        const size_t sl = spread_lds_bytes(c.fp64, c.n);
+        const std::array<int, 5> sk{c.fp64, c.deg, fused, snap, lds_tier(sl)};
+        auto it = sg.find(sk);
+        if (it == sg.end()) {
+            it = sg.emplace(sk, P.spread_groups.size()).first;
+            P.spread_groups.emplace_back();
+            Group& g = P.spread_groups.back();
+            g.fp64 = c.fp64;
+            g.deg = c.deg;
+            g.fused = fused;
+            g.snap = snap;
+        }
+        Group& g = P.spread_groups[it->second];
+        g.cls.push_back((int)ci);
+        g.lds[0] = std::max(g.lds[0], sl);
+        const size_t el = epilogue_lds_bytes(c.fp64, c.n, c.kmax, 1);
+        const std::array<int, 2> ek{c.fp64, lds_tier(el)};
+        std::vector<size_t>& cand = eg[ek];
+        size_t gi = SIZE_MAX;
+        for (size_t q : cand) {
+            bool clash = false;
+            for (int32_t t : c.tmpl_id) clash = clash || eg_tmpls[q][t];
+            if (!clash) {
+                gi = q;
+                break;
+            }
+        }
+        if (gi == SIZE_MAX) {
+            gi = P.epi_groups.size();
+            cand.push_back(gi);
+            P.epi_groups.emplace_back();
+            P.epi_groups.back().fp64 = c.fp64;
+            eg_tmpls.emplace_back((size_t)P.n_tmpls, (char)0);
+        }
+        for (int32_t t : c.tmpl_id) eg_tmpls[gi][t] = 1;
+        Group& e = P.epi_groups[gi];
+        e.cls.push_back((int)ci);
+        e.lds[0] = std::max(e.lds[0], epilogue_lds_bytes(c.fp64, c.n, c.kmax, 0));
+        e.lds[1] = std::max(e.lds[1], el);
+    }
+    for (Group& g : P.spread_groups) {
+        std::vector<SpreadArgs> tab;
+        std::vector<int64_t> off{0};
+        for (int ci : g.cls) {
+            const Class& c = *P.classes[ci];
+            tab.push_back(spread_args(P, c, c.chunks[0]));
+            off.push_back(off.back() + spread_blocks(c.chunks[0].count, c.parts));
+        }
+        g.blocks[0] = off.back();
+        g.d_tab.upload(tab, "class table");
+        g.d_off[0].upload(off, "class table");
+    }
+    for (Group& g : P.epi_groups) {
+        std::vector<EpilogueArgs> tab;
+        std::vector<int64_t> off[2];
+        off[0].push_back(0);
+        off[1].push_back(0);
+        for (int ci : g.cls) {
+            const Class& c = *P.classes[ci];
+            const EpilogueArgs e = epilogue_args(P, c, c.chunks[0]);
+            tab.push_back(e);
+            for (int m = 0; m < 2; ++m) off[m].push_back(off[m].back() + epilogue_blocks(e, m));
+        }
+        g.d_tab.upload(tab, "class table");
+        for (int m = 0; m < 2; ++m) {
+            g.blocks[m] = off[m].back();
+            g.d_off[m].upload(off[m], "class table");
+        }
+    }
 }
 
 void check_finite(nr_plan_s& P, const void* strain)
@@ -765,12 +936,61 @@ void run_front(nr_plan_s& P, Class& c, const Chunk& ch)
                  "spread kernel");
 }
 
-void lane_major(nr_plan_s& P, Class& c, const void* strain)
+// Lane-major strain copies of every class (one launch per destination precision).
+void lane_major(nr_plan_s& P, const void* strain)
 {
-    timed_launch(P, NR_STAGE_LAYOUT, [&] {
-        return launch_strain_lane_major((const SegDev*)c.d_segs.p, (int32_t)c.segs.size(), c.parts, strain,
-                                        P.strain_fp64, P.opt.strain_complex, c.d_strain.p, c.fp64, P.stream);
-    }, "strain layout");
+    for (int f = 0; f < 2; ++f)
+        if (!P.lm_segs[f].empty())
+            timed_launch(P, NR_STAGE_LAYOUT, [&] {
+                return launch_strain_lane_major((const SegDev*)P.d_lm_segs[f].p, (int32_t)P.lm_segs[f].size(),
+                                                strain, P.strain_fp64, P.opt.strain_complex, f, P.stream);
+            }, "strain layout");
+}
+
+// Batched mode: tau for staged classes, then one spread launch per group.
+void run_front_batched(nr_plan_s& P)
+{
+    for (auto& cp : P.classes) {
+        Class& c = *cp;
+        if (c.method != NR_METHOD_STAGED || c.chunks.empty()) continue;
+        SpreadArgs a = spread_args(P, c, c.chunks[0]);
+        timed_launch(P, NR_STAGE_TAU, [&] { return launch_tau(a, c.fp64, P.stream); }, "tau kernel");
+    }
+    for (Group& g : P.spread_groups) {
+        if (g.cls.size() == 1) {
+            Class& c = *P.classes[g.cls[0]];
+            SpreadArgs a = spread_args(P, c, c.chunks[0]);
+            timed_launch(P, NR_STAGE_SPREAD, [&] { return launch_spread(a, c.fp64, c.deg, g.fused, P.stream); },
+                         "spread kernel");
+            continue;
+        }
+        timed_launch(P, NR_STAGE_SPREAD, [&] {
+            return launch_spread_multi((const SpreadArgs*)g.d_tab.p, (const int64_t*)g.d_off[0].p, (int)g.cls.size(),
+                                       g.blocks[0], g.fp64, g.deg, g.fused, P.opt.strain_complex, g.snap, g.lds[0],
+                                       P.stream);
+        }, "spread kernel");
+    }
+}
+
+// Batched mode: one epilogue launch per group (mode 0 spectra, 1 segment sum).
+void run_epilogue_batched(nr_plan_s& P, int mode, const EpilogueOut& out)
+{
+    for (Group& g : P.epi_groups) {
+        if (g.cls.size() == 1) {
+            Class& c = *P.classes[g.cls[0]];
+            EpilogueArgs e = epilogue_args(P, c, c.chunks[0]);
+            timed_launch(P, NR_STAGE_EPILOGUE, [&] {
+                return mode ? launch_epilogue_sum(e, out, c.fp64, P.out_fp64, P.stream)
+                            : launch_epilogue_spectra(e, out, c.fp64, P.out_fp64, P.stream);
+            }, mode ? "segment sum" : "epilogue");
+            continue;
+        }
+        timed_launch(P, NR_STAGE_EPILOGUE, [&] {
+            return launch_epilogue_multi((const EpilogueArgs*)g.d_tab.p, (const int64_t*)g.d_off[mode].p,
+                                         (int)g.cls.size(), g.blocks[mode], mode, out, g.fp64, P.out_fp64,
+                                         g.lds[mode], P.stream);
+        }, mode ? "segment sum" : "epilogue");
+    }
 }
 
 void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid);
@@ -826,17 +1046,26 @@ void execute(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8
 
 void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid)
 {
-    for (auto& cp : P.classes) {
-        Class& c = *cp;
-        lane_major(P, c, strain);
-        for (const Chunk& ch : c.chunks) {
-            run_front(P, c, ch);
-            EpilogueArgs e = epilogue_args(P, c, ch);
-            e.spectra = spectra;
-            e.power = power;
-            if (spectra || power)
-                timed_launch(P, NR_STAGE_EPILOGUE,
-                             [&] { return launch_epilogue_spectra(e, c.fp64, P.out_fp64, P.stream); }, "epilogue");
+    EpilogueOut out{};
+    out.spectra = spectra;
+    out.power = power;
+    lane_major(P, strain);
+    if (P.batched) {
+        if (spectra || power) {
+            run_front_batched(P);
+            run_epilogue_batched(P, 0, out);
+        }
+    } else {
+        for (auto& cp : P.classes) {
+            Class& c = *cp;
+            for (const Chunk& ch : c.chunks) {
+                run_front(P, c, ch);
+                EpilogueArgs e = epilogue_args(P, c, ch);
+                if (spectra || power)
+                    timed_launch(P, NR_STAGE_EPILOGUE,
+                                 [&] { return launch_epilogue_spectra(e, out, c.fp64, P.out_fp64, P.stream); },
+                                 "epilogue");
+            }
         }
     }
     if (spectra || power || valid)
@@ -859,17 +1088,23 @@ void semicoherent(nr_plan_s& P, const void* strain, const double* w, void* stat,
 
 void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, void* stat, int32_t* n_used)
 {
+    EpilogueOut out{};
+    out.seg_weight = w;
+    out.stat = stat;
+    out.n_used = n_used;
+    lane_major(P, strain);
+    if (P.batched) {
+        run_front_batched(P);
+        run_epilogue_batched(P, 1, out);
+        return;
+    }
     for (auto& cp : P.classes) {
         Class& c = *cp;
-        lane_major(P, c, strain);
         for (const Chunk& ch : c.chunks) {
             run_front(P, c, ch);
             EpilogueArgs e = epilogue_args(P, c, ch);
-            e.seg_weight = w;
-            e.stat = stat;
-            e.n_used = n_used;
             timed_launch(P, NR_STAGE_EPILOGUE,
-                         [&] { return launch_epilogue_sum(e, c.fp64, P.out_fp64, P.stream); }, "segment sum");
+                         [&] { return launch_epilogue_sum(e, out, c.fp64, P.out_fp64, P.stream); }, "segment sum");
         }
     }
 }

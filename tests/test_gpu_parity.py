@@ -173,6 +173,54 @@ def test_ragged_batch_auto_precision(gpu):
         assert e <= bound, (i, t, e, w.seg_len[w.inst_seg[i]], w.n_bins[i])
 
 
+def test_ragged_batch_grouped_launches(gpu):
+    """Many kernel classes in one plan run as a few grouped launches; spectra
+    and segment sums still match the oracle class by class."""
+    import torch
+    from paper_2609_12476_amd import Plan, complex_view
+    say("ragged grouped launches")
+    w = synth.ragged_batch(n_inst=24, seed=21)
+    w.inst_tol = np.where(w.inst_tol < 1e-6, 1e-6, w.inst_tol)     # FP32 classes only
+    Xr, off, ok = oracle.spectra(w)
+    # every template of this batch has one instance: its segment sum is that
+    # instance's power
+    Sr, soff, used_r = np.abs(Xr) ** 2, off, ok.astype(np.int32)
+    with Plan.from_workload(w, precision="fp32") as p:
+        cls = p.classes()
+        say(f"  {len(cls)} classes, {p.info.n_chunks} spread launches, parts {sorted({c.parts for c in cls})}")
+        assert len(cls) > 1 and p.info.n_chunks < len(cls)
+        x = p.strain_tensor(w.strain, gpu)
+        sp, _, valid = p.execute(x)
+        stat, used = p.semicoherent_sum(x)
+        torch.cuda.synchronize()
+        X = complex_view(sp).cpu().numpy().astype(np.complex128)
+        S = stat.cpu().numpy().astype(np.float64)
+        used = used.cpu().numpy()
+    assert np.array_equal(valid.cpu().numpy(), ok) and np.array_equal(used, used_r)
+    errs = per_instance_errors(X, Xr, off, ok)
+    say(f"  spectra max rel {errs.max():.3e}")
+    assert errs.max() <= max(FP32_SPEC, float(w.inst_tol.max()))
+    for m in range(len(soff) - 1):
+        if used_r[m]:
+            e = rel(S[soff[m]:soff[m + 1]], Sr[soff[m]:soff[m + 1]])
+            assert e <= max(FP32_SUM, 10 * float(w.inst_tol[m])), (m, e)
+
+
+def test_classes_sharing_templates(gpu):
+    """Two FP32 classes (different kernel widths) hold instances of the same
+    templates: their segment-sum contributions must all arrive."""
+    say("classes sharing templates")
+    w = synth.semicoherent(hours=0.1, n_mc=3, n_sub=2, seed=5, snr=25.0)
+    w = w.subset(np.arange(w.n_inst))
+    w.inst_tol = np.where(np.arange(w.n_inst) % 2 == 0, 1e-6, 1e-5)
+    Sr, soff, used_r = oracle.semicoherent(w)
+    S, used, _ = run_sum(w, gpu, precision="fp32")
+    assert np.array_equal(used, used_r)
+    for m in range(len(soff) - 1):
+        if used_r[m]:
+            assert rel(S[soff[m]:soff[m + 1]], Sr[soff[m]:soff[m + 1]]) <= FP32_SUM
+
+
 # ------------------------------------------------------------- edge cases ----
 
 @pytest.mark.parametrize("L,K,mc", [(1, 3, 1e-2), (5, 8, 3e-2), (63, 17, 1e-2), (64, 16, 5e-4),
@@ -208,7 +256,7 @@ def test_identity_map_equals_fft(gpu):
     assert rel(X, np.fft.fft(x)) <= FP64_SPEC
 
 
-@pytest.mark.parametrize("parts", [1, 2, 4])
+@pytest.mark.parametrize("parts", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("sigma", [1.25, 2.0, 3.0])
 def test_parts_and_upsampling(gpu, parts, sigma):
     say(f"parts={parts} sigma={sigma}")
