@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--method", default="fused", choices=["fused", "staged"])
+    ap.add_argument("--method", default="fused", choices=["fused", "staged", "cellrun"])
     ap.add_argument("--hours", type=float, default=1.0)
     ap.add_argument("--n-mc", type=int, default=64)
     ap.add_argument("--no-fp64", action="store_true")
@@ -112,15 +112,15 @@ def other_workload(args, dev):
     with torch.cuda.stream(stream):
         if args.workload == "ragged_512":
             w = synth.ragged_batch(n_inst=512, seed=2)
-            kw = dict(precision="auto", use_graph=True, tune=args.tune)
+            kw = dict(precision="auto", use_graph=True, tune=args.tune, method=args.method)
             mode = "execute"
         elif args.workload == "paper_beta_bank":
             w = synth.paper_bank(hours=1.0).as_float32_strain()
-            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune)
+            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune, method=args.method)
             mode = "execute"
         else:
             w = synth.semicoherent(hours=6.0, n_mc=2048, n_sub=20, seed=3, tol=1e-6).as_float32_strain()
-            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune)
+            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune, method=args.method)
             mode = "sum"
         log(f"{w.name}: planning {w.n_inst} instances")
         t0 = time.perf_counter()
@@ -248,7 +248,8 @@ def main():
     elif dom == "spread":
         ops = algorithmic_ops(cls)
         achieved = ops / max(launches, 1) / (per_launch_ms * 1e-3) / 1e12
-        roof = {"kernel": "spread_kernel<float, fused>", "bound": "alu", "achieved": achieved,
+        kname = "spread_runs_kernel<float>" if args.method == "cellrun" else "spread_kernel<float, fused>"
+        roof = {"kernel": kname, "bound": "alu", "achieved": achieved,
                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                 "traffic": None, "ops_per_point": ops / pts}
     else:

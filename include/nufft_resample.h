@@ -80,7 +80,12 @@ typedef enum {
 typedef enum {
     NR_METHOD_AUTO = 0,   /* the library's choice (the fused kernel) */
     NR_METHOD_STAGED = 1, /* tau kernel writes a point stream; spreader reads it */
-    NR_METHOD_FUSED = 2   /* the spreader evaluates tau itself; no point stream */
+    NR_METHOD_FUSED = 2,  /* the spreader evaluates tau itself; no point stream; each
+                             lane takes a fixed run of consecutive samples */
+    NR_METHOD_CELLRUN = 3 /* fused; each lane takes the samples of one visit of the
+                             time series to one grid cell (found by binary search on
+                             the monotone cell index), so lanes never change cell
+                             inside a run and flush together */
 } nr_method;
 
 /* One segment of uniformly sampled strain (Sec. III: T_obs split into T_coh segments). */
@@ -168,7 +173,7 @@ typedef struct {
     double beta_es;     /* ES shape parameter */
     int64_t n_inst;     /* valid instances in the class */
     int64_t n_points;   /* sum of L over them */
-    int32_t method;          /* NR_METHOD_STAGED or NR_METHOD_FUSED */
+    int32_t method;          /* NR_METHOD_STAGED, NR_METHOD_FUSED or NR_METHOD_CELLRUN */
     int32_t flush_period;    /* spreader steps between collective flushes */
     int32_t snap;            /* 1: cumulative spreader moments with snapshots; 0: per cell */
     int32_t reserved;

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "nr_internal.hpp"
 
@@ -89,6 +90,10 @@ __device__ __forceinline__ double horner(const double* b, double x)
 // instance (Horner in FP64); instances whose series converges too slowly use
 // a * (-expm1((5/8) log1p(-y))).  Both forms avoid the cancellation of the
 // direct difference of two values of size 3/(5 beta).
+// FALLBACK: also the log1p/expm1 form (the tau kernel); the fused
+// spreaders only ever see series instances and leave it out, which keeps
+// their register count low.
+template <bool FALLBACK = true>
 __device__ __forceinline__ double dtau_of(const TauConsts& t, int j)
 {
     const double jd = (double)j;
@@ -102,7 +107,7 @@ __device__ __forceinline__ double dtau_of(const TauConsts& t, int j)
     default:
         break;
     }
-    if (t.ndeg > 0) {
+    if (!FALLBACK || t.ndeg > 0) {
         double acc = t.b[t.ndeg - 1];
         for (int k = t.ndeg - 2; k >= 0; --k) acc = fma(acc, jd, t.b[k]);
         return acc * jd;
@@ -117,9 +122,10 @@ struct Reduced {
     double pos, phase;
 };
 
+template <bool FALLBACK = true>
 __device__ __forceinline__ Reduced reduce_point(const TauConsts& t, int j)
 {
-    const double dt = dtau_of(t, j);
+    const double dt = dtau_of<FALLBACK>(t, j);
     Reduced r;
     r.pos = __builtin_amdgcn_fract(fma(t.df, dt, -t.hn));
     r.phase = __builtin_amdgcn_fract(t.fc * dt);
@@ -216,19 +222,13 @@ struct Decoded {
     T u, cr, ci;
 };
 
+// Heterodyned sample value c = x exp(-2 pi i phase).
 template <typename T, bool CPLX>
-__device__ __forceinline__ Decoded<T> decode(Reduced r, T xr, T xi, int n, const cpx<T>* tab)
+__device__ __forceinline__ void heterodyne(double phase, T xr, T xi, const cpx<T>* tab, T& cr, T& ci)
 {
-    Decoded<T> o;
-    const double S = r.pos * (double)n;           // (x - w/2) mod n, in cells
-    const double fl = floor(S);
-    // in [1, n + 1]; n + 1 (S rounded up to n) is cell 1 again, which the
-    // flush's single modulo step maps correctly
-    o.g = (int)fl + 1;
-    o.u = (T)fma(-2.0, S - fl, 1.0);
     // phase = k / N + theta / (2 pi), |theta| <= pi / N
     constexpr int B = PhaseTable<T>::bits;
-    const double sc = r.phase * (double)(1 << B);
+    const double sc = phase * (double)(1 << B);
     const double k = rint(sc);
     const T th = (T)((sc - k) * (6.283185307179586476925 / (double)(1 << B)));
     const cpx<T> e = tab[(int)k & ((1 << B) - 1)];
@@ -245,12 +245,25 @@ __device__ __forceinline__ Decoded<T> decode(Reduced r, T xr, T xi, int n, const
     const T er = e.x * cs - e.y * sn;
     const T ei = e.y * cs + e.x * sn;
     if (CPLX) {
-        o.cr = xr * er + xi * ei;
-        o.ci = xi * er - xr * ei;
+        cr = xr * er + xi * ei;
+        ci = xi * er - xr * ei;
     } else {
-        o.cr = xr * er;
-        o.ci = -xr * ei;
+        cr = xr * er;
+        ci = -xr * ei;
     }
+}
+
+template <typename T, bool CPLX>
+__device__ __forceinline__ Decoded<T> decode(Reduced r, T xr, T xi, int n, const cpx<T>* tab)
+{
+    Decoded<T> o;
+    const double S = r.pos * (double)n;           // (x - w/2) mod n, in cells
+    const double fl = floor(S);
+    // in [1, n + 1]; n + 1 (S rounded up to n) is cell 1 again, which the
+    // flush's single modulo step maps correctly
+    o.g = (int)fl + 1;
+    o.u = (T)fma(-2.0, S - fl, 1.0);
+    heterodyne<T, CPLX>(r.phase, xr, xi, tab, o.cr, o.ci);
     return o;
 }
 
@@ -404,7 +417,7 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock
             if (j < L) {
                 Reduced r;
                 if (FUSED)
-                    r = reduce_point(tc, j);
+                    r = reduce_point<false>(tc, j);
                 else
                     r = unpack_point<T>(pts[(int64_t)s * kWave]);
                 T xr, xi;
@@ -483,6 +496,151 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
     spread_block<T, D, FUSED, CPLX, SNAP>(a, blockIdx.x);
 }
 
+// ------------------------------------------------- cell-run schedule --
+//
+// x_j = df dtau_j - w/(2n) grows with j, so the unwrapped cell index
+// U_j = floor(x_j) n + floor(frac(x_j) n) never decreases and the samples
+// sharing one value of U form a contiguous run.  A wave takes 63 consecutive
+// values of U per round: lane v finds the first sample of run U_0 + 63 r + v
+// by a binary search of uniform length, the next lane's start ends its run,
+// every lane accumulates its run's moments without a cell change, and all
+// lanes flush together.  The strain is read as aligned quads of samples
+// from a plain per-segment copy.
+
+// U_j and the quantities of sample j that decide it.
+struct CellOf {
+    double x, pos, S, U;
+};
+
+__device__ __forceinline__ CellOf cell_of(const TauConsts& tc, int j, double nd, double dt)
+{
+    CellOf c;
+    c.x = fma(tc.df, dt, -tc.hn);
+    c.pos = __builtin_amdgcn_fract(c.x);
+    c.S = c.pos * nd;
+    c.U = fma(floor(c.x), nd, floor(c.S));
+    return c;
+}
+
+// Number of samples j < L with U_j < t.
+__device__ __forceinline__ int first_at_least(const TauConsts& tc, int L, double t, double nd)
+{
+    int pos = 0;
+    for (int step = 1 << (31 - __clz(L)); step > 0; step >>= 1) {
+        const int probe = min(pos + step, L) - 1;
+        const double U = cell_of(tc, probe, nd, dtau_of<false>(tc, probe)).U;
+        if (pos + step <= L && U < t) pos += step;
+    }
+    return pos;
+}
+
+template <typename E>
+struct alignas(16) Quad {
+    E v[4];
+};
+
+template <typename T, int D, bool CPLX>
+__device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t lblock)
+{
+    constexpr int NT = 1 << PhaseTable<T>::bits;
+    using E = typename std::conditional<CPLX, cpx<T>, T>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* lds = tab + NT;
+
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int parts = a.parts;
+    const int n = a.n, w = a.w;
+    cpx<T>* grid = lds + wave * n;
+    const cpx<T>* gtab = reinterpret_cast<const cpx<T>*>(a.phase_table);
+    for (int k = threadIdx.x; k < NT; k += kBlock) tab[k] = gtab[k];
+    for (int c = lane; c < n; c += kWave) grid[c] = cpx<T>{T(0), T(0)};
+    __syncthreads();
+
+    const int wpi = parts < 4 ? parts : 4;
+    int64_t item;
+    int part, slot = 0;
+    if (parts <= 4) {
+        item = lblock * (4 / parts) + wave / parts;
+        part = wave % parts;
+    } else {
+        item = lblock / (parts / 4);
+        slot = (int)(lblock % (parts / 4));
+        part = slot * 4 + wave;
+    }
+    const T* __restrict__ A = reinterpret_cast<const T*>(a.taps);
+
+    if (item < a.count) {
+        const InstDev d = a.inst[a.first + item];
+        TauConsts tc;
+        load_tau(tc, d, a.coef, half_width_periods(w, n));
+        const double nd = (double)n;
+        const int L = d.L;
+        const double U0 = cell_of(tc, 0, nd, dtau_of<false>(tc, 0)).U;
+        const double U1 = cell_of(tc, L - 1, nd, dtau_of<false>(tc, L - 1)).U;
+        const int rounds = uniform(((int)(U1 - U0) + 63) / 63);
+        const E* __restrict__ xs = reinterpret_cast<const E*>(a.strain_lm) + d.strain_off;
+        for (int r = part; r < rounds; r += parts) {
+            const double t = U0 + 63.0 * r + (double)lane;
+            const int js = first_at_least(tc, L, t, nd);
+            int je = __shfl_down(js, 1);
+            if (lane == kWave - 1 || !(t <= U1)) je = js;
+            Moments<T, D> M;
+            M.zero();
+            for (int q = js & ~3; q < je; q += 4) {
+                const Quad<E> xq = *reinterpret_cast<const Quad<E>*>(xs + q);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int j = q + e;
+                    if (j >= js && j < je) {
+                        const double dt = dtau_of<false>(tc, j);
+                        const CellOf c = cell_of(tc, j, nd, dt);
+                        const T u = (T)fma(-2.0, c.S - floor(c.S), 1.0);
+                        T xr, xi, cr, ci;
+                        if constexpr (CPLX) {
+                            xr = xq.v[e].x;
+                            xi = xq.v[e].y;
+                        } else {
+                            xr = xq.v[e];
+                            xi = T(0);
+                        }
+                        heterodyne<T, CPLX>(__builtin_amdgcn_fract(tc.fc * dt), xr, xi, tab, cr, ci);
+                        M.add(u, cr, ci);
+                    }
+                }
+            }
+            if (je > js) {
+                int g = (int)(t - nd * floor(t / nd));
+                if (g >= n) g -= n;
+                if (g < 0) g += n;
+                flush<T, D>(M, g + 1, A, grid, n, w);
+            }
+        }
+    }
+    __syncthreads();
+
+    if (item < a.count) {
+        const int first_wave = (wave / wpi) * wpi;
+        cpx<T>* out = reinterpret_cast<cpx<T>*>(a.grid) + (item * grid_slots(parts) + slot) * n;
+        for (int c = (wave % wpi) * kWave + lane; c < n; c += kWave * wpi) {
+            T r = T(0), i = T(0);
+            for (int q = 0; q < wpi; ++q) {
+                const cpx<T> gv = lds[(first_wave + q) * n + c];
+                r += gv.x;
+                i += gv.y;
+            }
+            out[c] = cpx<T>{r, i};
+        }
+    }
+}
+
+template <typename T, int D, bool CPLX>
+__global__ __launch_bounds__(kBlock) void spread_runs_kernel(SpreadArgs a)
+{
+    spread_runs_block<T, D, CPLX>(a, blockIdx.x);
+}
+
 // Class of workgroup b of a multi-class launch (block_off is ascending).
 __device__ __forceinline__ int class_of_block(const int64_t* __restrict__ block_off, int ncls, int64_t b)
 {
@@ -499,6 +657,16 @@ __global__ __launch_bounds__(kBlock) void spread_multi_kernel(const SpreadArgs* 
     const int c = class_of_block(block_off, ncls, blockIdx.x);
     const SpreadArgs a = tab[c];
     spread_block<T, D, FUSED, CPLX, SNAP>(a, (int64_t)blockIdx.x - block_off[c]);
+}
+
+template <typename T, int D, bool CPLX>
+__global__ __launch_bounds__(kBlock) void spread_runs_multi_kernel(const SpreadArgs* __restrict__ tab,
+                                                                   const int64_t* __restrict__ block_off,
+                                                                   int ncls)
+{
+    const int c = class_of_block(block_off, ncls, blockIdx.x);
+    const SpreadArgs a = tab[c];
+    spread_runs_block<T, D, CPLX>(a, (int64_t)blockIdx.x - block_off[c]);
 }
 
 // ------------------------------------------------------------------ FFT --
@@ -915,6 +1083,20 @@ static void launch_spread_k(const MultiSpread& m, dim3 grid, size_t lds, hipStre
     spread_multi_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(m.tab, m.block_off, m.ncls);
 }
 
+template <typename T, int D, bool CPLX>
+static void launch_runs_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStream_t st)
+{
+    allow_lds(spread_runs_kernel<T, D, CPLX>, lds);
+    spread_runs_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(a);
+}
+
+template <typename T, int D, bool CPLX>
+static void launch_runs_k(const MultiSpread& m, dim3 grid, size_t lds, hipStream_t st)
+{
+    allow_lds(spread_runs_multi_kernel<T, D, CPLX>, lds);
+    spread_runs_multi_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(m.tab, m.block_off, m.ncls);
+}
+
 template <typename T, int D, bool SNAP, typename A>
 static void launch_spread_s(const A& a, int fused, int cplx, dim3 grid, size_t lds, hipStream_t st)
 {
@@ -937,7 +1119,10 @@ static hipError_t launch_spread_d(const A& a, int fused, int cplx, int snap, int
 {
     dim3 grid((unsigned)blocks);
     constexpr bool snap_ok = snap_allowed<T, D>();
-    if (snap_ok && snap)
+    if (fused == 2) {
+        if (cplx) launch_runs_k<T, D, true>(a, grid, lds, st);
+        else launch_runs_k<T, D, false>(a, grid, lds, st);
+    } else if (snap_ok && snap)
         launch_spread_s<T, D, snap_ok>(a, fused, cplx, grid, lds, st);
     else
         launch_spread_s<T, D, false>(a, fused, cplx, grid, lds, st);

@@ -180,7 +180,7 @@ void validate(const nr_segment* segs, int32_t n_segs, const nr_template* tmpls, 
     if (!tmpls || n_tmpls <= 0) fail(NR_ERR_INVALID_ARG, "n_tmpls must be >= 1 with a template array");
     if (!(tol > 0.0 && tol <= 0.1) || !finite(tol)) fail(NR_ERR_INVALID_ARG, "tol must be in (0, 0.1]");
     if (o.precision < NR_FP32 || o.precision > NR_AUTO) fail(NR_ERR_INVALID_ARG, "unknown precision");
-    if (o.method < NR_METHOD_AUTO || o.method > NR_METHOD_FUSED) fail(NR_ERR_INVALID_ARG, "unknown method");
+    if (o.method < NR_METHOD_AUTO || o.method > NR_METHOD_CELLRUN) fail(NR_ERR_INVALID_ARG, "unknown method");
     if (o.sigma > 0.0 && !(o.sigma >= 1.25 && o.sigma <= 4.0))
         fail(NR_ERR_INVALID_ARG, "sigma must be in [1.25, 4]");
     if (o.parts != 0 && o.parts != 1 && o.parts != 2 && o.parts != 4 && o.parts != 8 && o.parts != 16)
@@ -302,11 +302,47 @@ int horner_series(const InstHost& h, double f_ref, double cyc_tol, std::vector<d
     return d;
 }
 
+// The method an option value stands for (AUTO: the fused sample-run spreader).
+int resolve_method(int m)
+{
+    return m == NR_METHOD_AUTO ? NR_METHOD_FUSED : m;
+}
+
+// Spreader code of a class for the launchers: 0 staged, 1 fused sample
+// runs, 2 fused cell runs.
+int spread_code(int method)
+{
+    return method == NR_METHOD_STAGED ? 0 : method == NR_METHOD_CELLRUN ? 2 : 1;
+}
+
+// Rounds of 63 cell runs that one cell-run instance needs: its unwrapped
+// cell index spans about n df dtau(L - 1) cells, plus the two ends.
+int cellrun_rounds(const InstHost& h, int64_t L, int n, double df)
+{
+    long double span;
+    if (h.beta == 0.0)
+        span = h.c * (long double)(L - 1);
+    else
+        span = h.a * (1.0L - powl(1.0L - (long double)h.y_max, 0.625L));
+    const long double cells = (long double)n * (long double)df * span + 2.0L;
+    return (int)std::min<long double>(1e6L, std::ceil(cells / 63.0L));
+}
+
 int default_parts(int64_t L)
 {
     if (L <= 16384) return 1;
     if (L <= 32768) return 2;
     return 4;
+}
+
+// Waves per cell-run instance: no more than its rounds; up to 16 in plans
+// too small to fill the GPU, else the sample-run rule.
+int cellrun_parts(int rounds, bool small_plan, int64_t L)
+{
+    const int cap = small_plan ? 16 : default_parts(L);
+    int p = 1;
+    while (p * 2 <= std::min(rounds, cap)) p *= 2;
+    return p;
 }
 
 // Waves per instance when the whole plan has too few waves to fill the chip:
@@ -441,7 +477,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     P.n_inst = inst ? n_inst : (int64_t)n_segs * n_tmpls;
     P.out_fp64 = o.precision != NR_FP32;
     P.strain_fp64 = P.out_fp64;
-    P.method = (o.method == NR_METHOD_STAGED) ? NR_METHOD_STAGED : NR_METHOD_FUSED;
+    P.method = resolve_method(o.method);
 
     const int64_t N = P.n_inst;
     P.inst_seg.resize(N);
@@ -503,6 +539,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     // kernel width per distinct tolerance, and the last class looked up
     std::map<std::pair<double, int>, int> width_of;
     ClassKey last_key{-1, -1, -1, -1, -1, -1, -1};
+    std::vector<double> series;
     size_t last_ci = 0;
     for (int64_t i = 0; i < N; ++i) {
         const nr_segment& g = P.segs[P.inst_seg[i]];
@@ -532,8 +569,18 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": grid size " + std::to_string(n) +
                                          " exceeds the supported maximum " + std::to_string(n_max) +
                                          " (lower n_bins or sigma)");
+        // tau series of the instance (ndeg < 0: the log1p/expm1 form)
+        const double df_i = t.df > 0.0 ? t.df : g.fs / (double)g.n_samples;
+        series.clear();
+        int ndeg = 0;
+        if (h.beta != 0.0) {
+            const double f_ref = std::fabs(t.f_lo) + (double)K * df_i + df_i;
+            ndeg = horner_series(h, f_ref, fp64 ? 1e-14 : 1e-11, series);
+        }
+        int method = resolve_method(o.method);
         int parts = o.parts ? o.parts : small_plan ? small_plan_parts(g.n_samples) : default_parts(g.n_samples);
-        int method = (o.method == NR_METHOD_STAGED) ? NR_METHOD_STAGED : NR_METHOD_FUSED;
+        if (method == NR_METHOD_CELLRUN && o.parts == 0)
+            parts = cellrun_parts(cellrun_rounds(h, g.n_samples, n, df_i), small_plan, g.n_samples);
         int flush = o.flush_period;
         int snap = o.moment_mode == 2 ? 1 : 0;
         if (o.tune) {
@@ -543,6 +590,10 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             flush = tu.flush;
             snap = tu.snap;
         }
+        // the fused spreaders carry only the series form of tau; instances
+        // that need log1p/expm1 get their points from the tau kernel
+        if (ndeg < 0) method = NR_METHOD_STAGED;
+        if (method == NR_METHOD_CELLRUN) snap = 0;  // moments restart with every run
         ClassKey key{fp64, w, n, parts, method, flush, snap};
         size_t ci;
         const bool same = !(key < last_key) && !(last_key < key);
@@ -577,20 +628,19 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         d.m0 = K / 2;
         d.fc = t.f_lo + (double)d.m0 * df;
         d.L = (int32_t)g.n_samples;
-        d.C = (int32_t)((g.n_samples + (int64_t)kWave * parts - 1) / ((int64_t)kWave * parts));
+        // cell runs read a plain copy of the segment (lane-major layout with C = 1)
+        d.C = method == NR_METHOD_CELLRUN
+                  ? 1
+                  : (int32_t)((g.n_samples + (int64_t)kWave * parts - 1) / ((int64_t)kWave * parts));
         d.K = K;
         d.inst = (int32_t)i;
         d.seg = P.inst_seg[i];
         d.a = (double)h.a;
         d.c = (double)h.c;
-        if (h.beta == 0.0) {
-            d.ndeg = 0;
-        } else {
-            const double f_ref = std::fabs(t.f_lo) + (double)K * df + df;
-            const double cyc_tol = fp64 ? 1e-14 : 1e-11;
+        d.ndeg = ndeg;
+        if (ndeg > 0) {
             d.coef_off = (int32_t)c.coef.size();
-            d.ndeg = horner_series(h, f_ref, cyc_tol, c.coef);
-            if (d.ndeg < 0) d.coef_off = 0;
+            c.coef.insert(c.coef.end(), series.begin(), series.end());
         }
         c.inst.push_back(d);
         c.kmax = std::max(c.kmax, K);
@@ -618,10 +668,10 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
                 sd.dst_off = c.strain_entries;
                 sd.L = d.L;
                 sd.C = d.C;
-                sd.parts = c.parts;
+                sd.parts = c.method == NR_METHOD_CELLRUN ? (int32_t)((d.L + kWave - 1) / kWave) : c.parts;
                 c.segs.push_back(sd);
                 seg_at[d.seg] = sd.dst_off;
-                c.strain_entries += (int64_t)c.parts * d.C * kWave;
+                c.strain_entries += (int64_t)sd.parts * d.C * kWave;
             }
             d.strain_off = seg_at[d.seg];
             d.pt_off = pt;
@@ -839,7 +889,7 @@ void build_groups(nr_plan_s& P)
     for (size_t ci = 0; ci < P.classes.size(); ++ci) {
         const Class& c = *P.classes[ci];
         if (c.inst.empty()) continue;
-        const int fused = c.method == NR_METHOD_FUSED;
+        const int fused = spread_code(c.method);
         const int snap = (c.snap && !c.fp64 && c.deg <= 12) ? 1 : 0;
         const size_t sl = spread_lds_bytes(c.fp64, c.n);
         const std::array<int, 5> sk{c.fp64, c.deg, fused, snap, lds_tier(sl)};
@@ -932,7 +982,7 @@ void run_front(nr_plan_s& P, Class& c, const Chunk& ch)
     if (c.method == NR_METHOD_STAGED)
         timed_launch(P, NR_STAGE_TAU, [&] { return launch_tau(a, c.fp64, P.stream); }, "tau kernel");
     timed_launch(P, NR_STAGE_SPREAD,
-                 [&] { return launch_spread(a, c.fp64, c.deg, c.method == NR_METHOD_FUSED, P.stream); },
+                 [&] { return launch_spread(a, c.fp64, c.deg, spread_code(c.method), P.stream); },
                  "spread kernel");
 }
 
@@ -1170,12 +1220,14 @@ Tuned tune_shape(const nr_options& base, const nr_segment& g, const nr_template&
     used.alloc(sizeof(int32_t), "tuning output");
     hip_check(hipMemset(stat.p, 0, (size_t)t.n_bins * 8), "tuning output");
     Tuned best{NR_METHOD_FUSED, default_parts(L), 0, 0, INFINITY};
-    for (int method : {NR_METHOD_FUSED, NR_METHOD_STAGED})
+    for (int method : {NR_METHOD_FUSED, NR_METHOD_STAGED, NR_METHOD_CELLRUN})
         for (int parts : {1, 2, 4}) {
             if (parts > 1 && L < (int64_t)kWave * parts * 16) continue;
             for (int flush : {4, 16, 64})
                 for (int snap : {0, 1}) {
                     if (snap && fp64) continue;  // cumulative snapshots are an FP32-class option
+                    // cell runs flush once per run and restart their moments
+                    if (method == NR_METHOD_CELLRUN && (flush != 16 || snap)) continue;
                     const double us = time_config(base, g, t, tol, fp64, method, parts, flush, snap, strain.p,
                                                   stat.p, (int32_t*)used.p, batch);
                     if (us < best.us_per_inst) best = Tuned{method, parts, flush, snap, us};

@@ -22,12 +22,13 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_semicoherent_1h_sampled(gpu):
-    say("full-size 1 h workload, sampled")
+@pytest.mark.parametrize("method", ["fused", "cellrun"])
+def test_semicoherent_1h_sampled(gpu, method):
+    say(f"full-size 1 h workload, sampled, {method}")
     import torch
     from paper_2609_12476_amd import Plan, complex_view
     w = synth.semicoherent(hours=1.0, n_mc=64, n_sub=20, seed=1).as_float32_strain()
-    with Plan.from_workload(w, tol=1e-6, precision="fp32", method="fused") as p:
+    with Plan.from_workload(w, tol=1e-6, precision="fp32", method=method) as p:
         assert p.info.n_inst == 153600
         x = p.strain_tensor(w.strain, gpu)
         sp, _, valid = p.execute(x, want=("spectra", "valid"))

@@ -64,7 +64,7 @@ def per_instance_errors(X, Xr, off, ok):
 
 # ------------------------------------------------------------ single segment --
 
-@pytest.mark.parametrize("method", ["fused", "staged"])
+@pytest.mark.parametrize("method", ["fused", "staged", "cellrun"])
 def test_single_segment_fp64(gpu, method):
     say(f"single_segment fp64 {method}")
     w = synth.single_segment()
@@ -78,7 +78,7 @@ def test_single_segment_fp64(gpu, method):
     assert np.allclose(P, np.abs(X) ** 2, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("method", ["fused", "staged"])
+@pytest.mark.parametrize("method", ["fused", "staged", "cellrun"])
 def test_single_segment_fp32(gpu, method):
     say(f"single_segment fp32 {method}")
     w = synth.single_segment()
@@ -103,8 +103,8 @@ def test_analytic_chirp_collapse_on_gpu(gpu):
 
 # ------------------------------------------------------------ semicoherent ----
 
-@pytest.mark.parametrize("prec,method", [("fp32", "fused"), ("fp32", "staged"), ("fp64", "fused"),
-                                         ("fp64", "staged")])
+@pytest.mark.parametrize("prec,method", [("fp32", "fused"), ("fp32", "staged"), ("fp32", "cellrun"),
+                                         ("fp64", "fused"), ("fp64", "staged"), ("fp64", "cellrun")])
 def test_semicoherent_small(gpu, prec, method):
     say(f"semicoherent small {prec} {method}")
     w = synth.semicoherent(hours=0.1, n_mc=4, n_sub=3, seed=3, snr=30.0)
@@ -226,16 +226,18 @@ def test_classes_sharing_templates(gpu):
 @pytest.mark.parametrize("L,K,mc", [(1, 3, 1e-2), (5, 8, 3e-2), (63, 17, 1e-2), (64, 16, 5e-4),
                                     (65, 9, 1e-1), (130, 40, 2e-2), (1000, 1, 1e-2), (257, 101, 0.0)])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_small_and_ragged_sizes(gpu, L, K, mc, prec):
-    say(f"edge L={L} K={K} mc={mc} {prec}")
+@pytest.mark.parametrize("method", ["fused", "cellrun"])
+def test_small_and_ragged_sizes(gpu, L, K, mc, prec, method):
+    say(f"edge L={L} K={K} mc={mc} {prec} {method}")
     w = synth.random_small(L + K, L, K, mc, f0=50.0, fs=64.0, t_start=3.0)
     Xr, off, ok = oracle.spectra(w)
-    X, P, valid, _, _ = run_plan(w, gpu, precision=prec, tol=1e-6 if prec == "fp32" else 1e-10)
+    X, P, valid, _, _ = run_plan(w, gpu, precision=prec, method=method,
+                                 tol=1e-6 if prec == "fp32" else 1e-10)
     assert valid[0] == ok[0] == 1
     assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
 
 
-@pytest.mark.parametrize("method", ["fused", "staged"])
+@pytest.mark.parametrize("method", ["fused", "staged", "cellrun"])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_complex_strain(gpu, prec, method):
     say(f"complex strain {prec} {method}")
@@ -258,13 +260,33 @@ def test_identity_map_equals_fft(gpu):
 
 @pytest.mark.parametrize("parts", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("sigma", [1.25, 2.0, 3.0])
-def test_parts_and_upsampling(gpu, parts, sigma):
-    say(f"parts={parts} sigma={sigma}")
+@pytest.mark.parametrize("method", ["fused", "cellrun"])
+def test_parts_and_upsampling(gpu, parts, sigma, method):
+    say(f"parts={parts} sigma={sigma} {method}")
     w = synth.single_segment()
     Xr, _, _ = oracle.spectra(w)
-    X, _, _, _, cls = run_plan(w, gpu, precision="fp64", tol=1e-9, parts=parts, sigma=sigma)
+    X, _, _, _, cls = run_plan(w, gpu, precision="fp64", tol=1e-9, parts=parts, sigma=sigma, method=method)
     assert cls[0].parts == parts
     assert rel(X, Xr) <= FP64_SPEC
+
+
+@pytest.mark.parametrize("method", ["fused", "cellrun"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_near_coalescence_uses_tau_kernel(gpu, method, prec):
+    """A template so close to coalescence that tau needs the log1p/expm1 form:
+    the plan routes it through the tau kernel (staged) and stays exact."""
+    import math
+    say(f"near coalescence {method} {prec}")
+    w = synth.random_small(77, 4096, 64, 1e-1, f0=50.0, fs=64.0, t_start=800.0)
+    b = synth.chirp_beta(1e-1, 50.0)
+    assert 1 - (8 / 3) * b * (800.0 + 4095 / 64.0) > 0           # still valid at the end
+    Xr, off, ok = oracle.spectra(w)
+    assert ok[0]
+    X, _, valid, _, cls = run_plan(w, gpu, precision=prec, method=method,
+                                   tol=1e-6 if prec == "fp32" else 1e-10)
+    say(f"  methods {[c.method for c in cls]}, series terms {[c.series_terms for c in cls]}")
+    assert valid[0] == 1 and cls[0].method == 1
+    assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
 
 
 def test_invalid_instances_are_zero_and_flagged(gpu):
