@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 # VALU lane-operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (one FP32 or FP64 FMA per lane per cycle without packed FP32).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+METHOD_NAME = {1: "staged", 2: "fused", 3: "cellrun"}
 
 
 def parse():
@@ -44,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--method", default="fused", choices=["fused", "staged", "cellrun"])
+    ap.add_argument("--method", default="auto", choices=["auto", "fused", "staged", "cellrun"])
     ap.add_argument("--hours", type=float, default=1.0)
     ap.add_argument("--n-mc", type=int, default=64)
     ap.add_argument("--no-fp64", action="store_true")
@@ -220,7 +221,8 @@ def main():
         "config": {"workload": f"semicoherent_{args.hours:g}h_{w.n_seg}seg_{args.n_mc}mc_x20subbands_256Hz",
                    "instances": int(info.n_inst), "valid_instances": int(info.n_valid),
                    "samples_per_segment": int(w.seg_len[0]), "bins_per_spectrum": 30,
-                   "tol": 1e-6, "sigma": 2.0, "method": args.method, "kernel_width": cls[0].w,
+                   "tol": 1e-6, "sigma": 2.0, "method": args.method,
+                   "spreaders": sorted({METHOD_NAME[c.method] for c in cls}), "kernel_width": cls[0].w,
                    "grid": cls[0].n, "degree": cls[0].degree, "parallelism": "single_gpu"},
         "all_instance_rate": info.n_inst * args.steps / el,
     }
@@ -248,7 +250,7 @@ def main():
     elif dom == "spread":
         ops = algorithmic_ops(cls)
         achieved = ops / max(launches, 1) / (per_launch_ms * 1e-3) / 1e12
-        kname = "spread_runs_kernel<float>" if args.method == "cellrun" else "spread_kernel<float, fused>"
+        kname = "spread_runs_kernel<float>" if cls[0].method == 3 else "spread_kernel<float, fused>"
         roof = {"kernel": kname, "bound": "alu", "achieved": achieved,
                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                 "traffic": None, "ops_per_point": ops / pts}

@@ -78,7 +78,10 @@ typedef enum {
 } nr_precision;
 
 typedef enum {
-    NR_METHOD_AUTO = 0,   /* the library's choice (the fused kernel) */
+    NR_METHOD_AUTO = 0,   /* per instance: NR_METHOD_CELLRUN when its time series spends
+                             at least 24 samples in each grid cell it visits or its
+                             spreader workgroup needs at most 1/5 of a compute unit's
+                             LDS; else NR_METHOD_FUSED */
     NR_METHOD_STAGED = 1, /* tau kernel writes a point stream; spreader reads it */
     NR_METHOD_FUSED = 2,  /* the spreader evaluates tau itself; no point stream; each
                              lane takes a fixed run of consecutive samples */

@@ -36,6 +36,7 @@ struct InstDev {
     int32_t seg;        // segment index
     int32_t ndeg;       // tau: 0 identity; > 0 Horner degree in the sample index; < 0 log1p/expm1
     int32_t coef_off;   // first Horner coefficient of this instance
+    int32_t entry;      // position in the class's template-major instance list
 };
 
 // One segment of a class: where its samples are and where its lane-major copy goes.
@@ -101,6 +102,9 @@ struct EpilogueArgs {
     int32_t tmpl_count;
     int32_t slots;                 // partial grids per instance
     int32_t kmax;                  // largest K of the class (LDS sizing of the segment sum)
+    // two-pass segment sum: power rows of the class, one per list entry
+    int64_t row_base;              // first element of the class's rows (row e at row_base + e kmax)
+    const int32_t* entry_seg;      // segment of each list entry
 };
 
 // Per-call pointers of the epilogue (the same for every class of a plan).
@@ -110,10 +114,12 @@ struct EpilogueOut {
     const double* seg_weight;
     void* stat;
     int32_t* n_used;
+    void* rows;              // power rows of the two-pass segment sum (first pass output)
 };
 
 // Launch wrappers (defined in nr_kernels.hip).
-hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, const void* strain,
+// max_entries: the largest parts * C * 64 of the segments (sizes the grid).
+hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int64_t max_entries, const void* strain,
                                     int strain_fp64, int strain_complex, int dst_fp64, hipStream_t st);
 // One launch over several classes of the same kernel instantiation: tab
 // holds their arguments (device), block_off[ncls + 1] their first workgroup.
@@ -129,6 +135,11 @@ hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st);
 hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st);
 hipError_t launch_epilogue_spectra(const EpilogueArgs& a, const EpilogueOut& out, int fp64,
                                    int out_fp64, hipStream_t st);
+// Second pass of the two-pass segment sum: stat += weighted sums of the
+// power rows of each class template (one workgroup per template).
+hipError_t launch_rows_sum(const EpilogueArgs& a, const EpilogueOut& out, int out_fp64, hipStream_t st);
+hipError_t launch_rows_sum_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
+                                 EpilogueOut out, int out_fp64, hipStream_t st);
 hipError_t launch_epilogue_sum(const EpilogueArgs& a, const EpilogueOut& out, int fp64, int out_fp64,
                                hipStream_t st);
 hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,

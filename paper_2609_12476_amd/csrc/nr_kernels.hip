@@ -22,6 +22,7 @@
 // sum_j c_j exp(-2 pi i m df dtau_j) = X(f_c + m df).
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <type_traits>
 
@@ -113,6 +114,39 @@ __device__ __forceinline__ double dtau_of(const TauConsts& t, int j)
         return acc * jd;
     }
     return t.a * (-expm1(0.625 * log1p(-t.c * jd)));
+}
+
+// dtau of the four samples j0 .. j0+3 of a quad (series form only): one
+// dispatch on the degree for all four.
+template <int N>
+__device__ __forceinline__ void horner4(const double* b, int j0, double* out)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = horner<N>(b, (double)(j0 + e));
+}
+
+__device__ __forceinline__ void dtau4(const TauConsts& t, int j0, double* out)
+{
+    switch (t.ndeg) {
+    case 0:
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[e] = (double)(j0 + e) * t.c;
+        return;
+#define NR_H4(N) \
+    case N: horner4<N>(t.bc, j0, out); return;
+        NR_H4(1) NR_H4(2) NR_H4(3) NR_H4(4) NR_H4(5) NR_H4(6) NR_H4(7) NR_H4(8) NR_H4(9) NR_H4(10)
+        NR_H4(11) NR_H4(12) NR_H4(13) NR_H4(14) NR_H4(15) NR_H4(16)
+#undef NR_H4
+    default:
+        break;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double jd = (double)(j0 + e);
+        double acc = t.b[t.ndeg - 1];
+        for (int k = t.ndeg - 2; k >= 0; --k) acc = fma(acc, jd, t.b[k]);
+        out[e] = acc * jd;
+    }
 }
 
 // The two reductions modulo one period, in FP64:
@@ -222,13 +256,12 @@ struct Decoded {
     T u, cr, ci;
 };
 
-// Heterodyned sample value c = x exp(-2 pi i phase).
+// Heterodyned sample value c = x exp(-2 pi i sc / N), N = 2^B table entries:
+// sc = k + theta N / (2 pi), |theta| <= pi / N.
 template <typename T, bool CPLX>
-__device__ __forceinline__ void heterodyne(double phase, T xr, T xi, const cpx<T>* tab, T& cr, T& ci)
+__device__ __forceinline__ void heterodyne_scaled(double sc, T xr, T xi, const cpx<T>* tab, T& cr, T& ci)
 {
-    // phase = k / N + theta / (2 pi), |theta| <= pi / N
     constexpr int B = PhaseTable<T>::bits;
-    const double sc = phase * (double)(1 << B);
     const double k = rint(sc);
     const T th = (T)((sc - k) * (6.283185307179586476925 / (double)(1 << B)));
     const cpx<T> e = tab[(int)k & ((1 << B) - 1)];
@@ -251,6 +284,30 @@ __device__ __forceinline__ void heterodyne(double phase, T xr, T xi, const cpx<T
         cr = xr * er;
         ci = -xr * ei;
     }
+}
+
+// The same from the phase in cycles.
+template <typename T, bool CPLX>
+__device__ __forceinline__ void heterodyne(double phase, T xr, T xi, const cpx<T>* tab, T& cr, T& ci)
+{
+    heterodyne_scaled<T, CPLX>(phase * (double)(1 << PhaseTable<T>::bits), xr, xi, tab, cr, ci);
+}
+
+// Fused path: cell and position straight from dtau.  S = x n with
+// x = df dtau - w/(2n); g = floor(S) + 1 is the unwrapped cell of the
+// support's first tap (the flush reduces it mod n) and frac(S) =
+// frac(frac(x) n) its position in that cell.
+template <typename T, bool CPLX>
+__device__ __forceinline__ Decoded<T> decode_dt(double dt, double dfn, double hnn, double fcs, T xr, T xi,
+                                                const cpx<T>* tab)
+{
+    Decoded<T> o;
+    const double S = fma(dfn, dt, -hnn);
+    const double fl = floor(S);
+    o.g = (int)fl + 1;
+    o.u = (T)fma(-2.0, S - fl, 1.0);
+    heterodyne_scaled<T, CPLX>(fcs * dt, xr, xi, tab, o.cr, o.ci);
+    return o;
 }
 
 template <typename T, bool CPLX>
@@ -314,6 +371,9 @@ template <typename T, int D>
 __device__ __forceinline__ void flush(const Moments<T, D>& M, int g, const T* __restrict__ A,
                                       cpx<T>* grid, int n, int w)
 {
+    // g may be any integer (an unwrapped cell index): reduce it mod n once
+    g %= n;
+    if (g < 0) g += n;
     for (int t = 0; t < w; ++t) {
         const T* At = A + t * (D + 1);
         T vr = T(0), vi = T(0);
@@ -403,6 +463,9 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock
                   : reinterpret_cast<const P*>(a.points) + (d.pt_off - a.pt_base) + row0;
         const int64_t xs0 = d.strain_off + row0;
         const int fmask = a.flush_period - 1;
+        // fused: grid position in cells and phase in table steps per unit dtau
+        const double dfn = tc.df * (double)n, hnn = tc.hn * (double)n;
+        const double fcs = tc.fc * (double)(1 << PhaseTable<T>::bits);
 
         // SNAP: M cumulative, E = snapshot at the end of the parked cell,
         //       S = snapshot at its start.
@@ -411,15 +474,12 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock
         M.zero();
         E.zero();
         if (SNAP) S.zero();
-        int g_cur = -1, g_pend = -1;
+        // cells are unwrapped integers on the fused path (any sign)
+        constexpr int kNone = INT_MIN;
+        int g_cur = kNone, g_pend = kNone;
         for (int s = 0; s < C; ++s) {
             const int j = v * C + s;
             if (j < L) {
-                Reduced r;
-                if (FUSED)
-                    r = reduce_point<false>(tc, j);
-                else
-                    r = unpack_point<T>(pts[(int64_t)s * kWave]);
                 T xr, xi;
                 if (CPLX) {
                     const cpx<T> xv = reinterpret_cast<const cpx<T>*>(a.strain_lm)[xs0 + (int64_t)s * kWave];
@@ -429,16 +489,17 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock
                     xr = reinterpret_cast<const T*>(a.strain_lm)[xs0 + (int64_t)s * kWave];
                     xi = T(0);
                 }
-                const Decoded<T> q = decode<T, CPLX>(r, xr, xi, n, tab);
+                const Decoded<T> q = FUSED ? decode_dt<T, CPLX>(dtau_of<false>(tc, j), dfn, hnn, fcs, xr, xi, tab)
+                                           : decode<T, CPLX>(unpack_point<T>(pts[(int64_t)s * kWave]), xr, xi, n, tab);
                 if (q.g != g_cur) {
-                    if (g_cur >= 0) {
+                    if (g_cur != kNone) {
                         if (SNAP) {
-                            if (g_pend >= 0) {
+                            if (g_pend != kNone) {
                                 flush_diff<T, D>(E, S, g_pend, A, grid, n, w);
                                 S = E;
                             }
                         } else {
-                            if (g_pend >= 0) flush<T, D>(E, g_pend, A, grid, n, w);
+                            if (g_pend != kNone) flush<T, D>(E, g_pend, A, grid, n, w);
                         }
                         E = M;
                         g_pend = g_cur;
@@ -449,26 +510,26 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock
                 M.add(q.u, q.cr, q.ci);
             }
             if ((s & fmask) == fmask) {
-                if (g_pend >= 0) {
+                if (g_pend != kNone) {
                     if (SNAP) {
                         flush_diff<T, D>(E, S, g_pend, A, grid, n, w);
                         S = E;
                     } else {
                         flush<T, D>(E, g_pend, A, grid, n, w);
                     }
-                    g_pend = -1;
+                    g_pend = kNone;
                 }
             }
         }
         if (SNAP) {
-            if (g_pend >= 0) {
+            if (g_pend != kNone) {
                 flush_diff<T, D>(E, S, g_pend, A, grid, n, w);
                 S = E;
             }
-            if (g_cur >= 0) flush_diff<T, D>(M, S, g_cur, A, grid, n, w);
+            if (g_cur != kNone) flush_diff<T, D>(M, S, g_cur, A, grid, n, w);
         } else {
-            if (g_pend >= 0) flush<T, D>(E, g_pend, A, grid, n, w);
-            if (g_cur >= 0) flush<T, D>(M, g_cur, A, grid, n, w);
+            if (g_pend != kNone) flush<T, D>(E, g_pend, A, grid, n, w);
+            if (g_cur != kNone) flush<T, D>(M, g_cur, A, grid, n, w);
         }
     }
     __syncthreads();
@@ -581,6 +642,9 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
         const double U1 = cell_of(tc, L - 1, nd, dtau_of<false>(tc, L - 1)).U;
         const int rounds = uniform(((int)(U1 - U0) + 63) / 63);
         const E* __restrict__ xs = reinterpret_cast<const E*>(a.strain_lm) + d.strain_off;
+        // per-sample scales: grid position in cells and phase in table steps
+        const double dfn = tc.df * nd, hnn = tc.hn * nd;
+        const double fcs = tc.fc * (double)(1 << PhaseTable<T>::bits);
         for (int r = part; r < rounds; r += parts) {
             const double t = U0 + 63.0 * r + (double)lane;
             const int js = first_at_least(tc, L, t, nd);
@@ -588,26 +652,29 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
             if (lane == kWave - 1 || !(t <= U1)) je = js;
             Moments<T, D> M;
             M.zero();
+            // whole quads; samples outside the run enter with zero strength
+            // (they lie in the padded copy and have finite positions)
             for (int q = js & ~3; q < je; q += 4) {
                 const Quad<E> xq = *reinterpret_cast<const Quad<E>*>(xs + q);
+                double dt[4];
+                dtau4(tc, q, dt);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int j = q + e;
-                    if (j >= js && j < je) {
-                        const double dt = dtau_of<false>(tc, j);
-                        const CellOf c = cell_of(tc, j, nd, dt);
-                        const T u = (T)fma(-2.0, c.S - floor(c.S), 1.0);
-                        T xr, xi, cr, ci;
-                        if constexpr (CPLX) {
-                            xr = xq.v[e].x;
-                            xi = xq.v[e].y;
-                        } else {
-                            xr = xq.v[e];
-                            xi = T(0);
-                        }
-                        heterodyne<T, CPLX>(__builtin_amdgcn_fract(tc.fc * dt), xr, xi, tab, cr, ci);
-                        M.add(u, cr, ci);
+                    const bool in = (j >= js) & (j < je);
+                    // position in the cell: frac(x n) = frac(frac(x) n)
+                    const double rr = __builtin_amdgcn_fract(fma(dfn, dt[e], -hnn));
+                    const T u = (T)fma(-2.0, rr, 1.0);
+                    T xr, xi, cr, ci;
+                    if constexpr (CPLX) {
+                        xr = in ? xq.v[e].x : T(0);
+                        xi = in ? xq.v[e].y : T(0);
+                    } else {
+                        xr = in ? xq.v[e] : T(0);
+                        xi = T(0);
                     }
+                    heterodyne_scaled<T, CPLX>(fcs * dt[e], xr, xi, tab, cr, ci);
+                    M.add(u, cr, ci);
                 }
             }
             if (je > js) {
@@ -838,14 +905,71 @@ __device__ __forceinline__ void epilogue_spectra_block(const EpilogueArgs& a, co
     const T* __restrict__ dec = reinterpret_cast<const T*>(a.dec);
     cpx<O>* sp = reinterpret_cast<cpx<O>*>(o.spectra);
     O* pw = reinterpret_cast<O*>(o.power);
+    O* rw = o.rows ? reinterpret_cast<O*>(o.rows) + a.row_base + (int64_t)d.entry * a.kmax : nullptr;
     for (int k = tid; k < d.K; k += ts) {
         int l = k - d.m0;
         if (l < 0) l += n;
         const T f = dec[l];
         const cpx<T> X = cpx<T>{res[l].x * f, res[l].y * f};
         if (sp) sp[d.bin_off + k] = cpx<O>{(O)X.x, (O)X.y};
-        if (pw) pw[d.bin_off + k] = (O)X.x * (O)X.x + (O)X.y * (O)X.y;
+        const O p = (O)X.x * (O)X.x + (O)X.y * (O)X.y;
+        if (pw) pw[d.bin_off + k] = p;
+        if (rw) rw[k] = p;
     }
+}
+
+// Second pass of the segment sum: the rows of one class template are
+// contiguous (template-major list order); threads split them by row in a
+// fixed pattern, sum in FP64 and combine the partial sums in order.
+template <typename O>
+__device__ __forceinline__ void rows_sum_block(const EpilogueArgs& a, const EpilogueOut& o, int64_t lblock)
+{
+    __shared__ double part[kBlock];
+    const int ct = a.tmpl_first + (int)lblock;
+    const int64_t lo = a.tmpl_list_off[ct], hi = a.tmpl_list_off[ct + 1];
+    if (hi <= lo) return;  // uniform across the workgroup
+    const int K = a.inst[a.tmpl_list[lo]].K;
+    const O* __restrict__ rows = reinterpret_cast<const O*>(o.rows) + a.row_base;
+    O* stat = reinterpret_cast<O*>(o.stat) + a.tmpl_stat_off[ct];
+    const int span = K < kBlock ? K : kBlock;
+    const int nsub = kBlock / span;
+    const int t = threadIdx.x;
+    const int sub = t / span, kk = t - sub * span;
+    for (int k0 = 0; k0 < K; k0 += span) {
+        const int k = k0 + kk;
+        double acc = 0.0;
+        if (sub < nsub && k < K) {
+            for (int64_t e = lo + sub; e < hi; e += nsub) {
+                const double wgt = o.seg_weight ? o.seg_weight[a.entry_seg[e]] : 1.0;
+                acc += wgt * (double)rows[e * a.kmax + k];
+            }
+        }
+        part[t] = acc;
+        __syncthreads();
+        if (t < span && k0 + t < K) {
+            double s = 0.0;
+            for (int q = 0; q < nsub; ++q) s += part[q * span + t];
+            stat[k0 + t] = (O)((double)stat[k0 + t] + s);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && o.n_used) o.n_used[a.tmpl_id[ct]] += (int32_t)(hi - lo);
+}
+
+template <typename O>
+__global__ __launch_bounds__(kBlock) void rows_sum_kernel(EpilogueArgs a, EpilogueOut o)
+{
+    rows_sum_block<O>(a, o, blockIdx.x);
+}
+
+template <typename O>
+__global__ __launch_bounds__(kBlock) void rows_sum_multi_kernel(const EpilogueArgs* __restrict__ tab,
+                                                                const int64_t* __restrict__ block_off, int ncls,
+                                                                EpilogueOut o)
+{
+    const int c = class_of_block(block_off, ncls, blockIdx.x);
+    const EpilogueArgs a = tab[c];
+    rows_sum_block<O>(a, o, (int64_t)blockIdx.x - block_off[c]);
 }
 
 // Segment sum: one workgroup per template; its instances inside the chunk
@@ -947,47 +1071,52 @@ __global__ __launch_bounds__(kBlock) void epilogue_multi_kernel(const EpilogueAr
 
 // ------------------------------------------------------------ utilities --
 
-// One workgroup per class segment: every part's rows of its lane-major copy.
+// Lane-major copies: blockIdx.x picks the class segment, blockIdx.y and the
+// thread stride over its entries in order, so the stores are contiguous.
 template <typename Ti, typename To>
 __global__ __launch_bounds__(kBlock) void strain_lane_major_kernel(const SegDev* __restrict__ segs,
                                                                    const Ti* __restrict__ src, int cplx)
 {
     const SegDev sd = segs[blockIdx.x];
     To* __restrict__ dst = reinterpret_cast<To*>(sd.dst);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int part = 0; part < sd.parts; ++part) {
-        const int64_t v = (int64_t)part * kWave + lane;
-        const int64_t row0 = sd.dst_off + (int64_t)part * sd.C * kWave + lane;
-        for (int s = wave; s < sd.C; s += 4) {
-            const int64_t j = v * sd.C + s;
-            const int64_t o = row0 + (int64_t)s * kWave;
-            if (cplx) {
-                To re = To(0), im = To(0);
-                if (j < sd.L) {
-                    re = (To)src[2 * (sd.src_off + j)];
-                    im = (To)src[2 * (sd.src_off + j) + 1];
-                }
-                dst[2 * o] = re;
-                dst[2 * o + 1] = im;
-            } else {
-                dst[o] = (j < sd.L) ? (To)src[sd.src_off + j] : To(0);
+    const uint32_t run = (uint32_t)sd.C * kWave;  // entries of 64 lane runs
+    const uint32_t total = (uint32_t)sd.parts * run;
+    for (uint32_t o = blockIdx.y * kBlock + threadIdx.x; o < total; o += kBlock * gridDim.y) {
+        const uint32_t blk = o / run, rem = o - blk * run;
+        const uint32_t srow = rem / kWave, lane = rem - srow * kWave;
+        const int64_t j = (int64_t)(blk * kWave + lane) * sd.C + srow;
+        const int64_t at = sd.dst_off + o;
+        if (cplx) {
+            To re = To(0), im = To(0);
+            if (j < sd.L) {
+                re = (To)src[2 * (sd.src_off + j)];
+                im = (To)src[2 * (sd.src_off + j) + 1];
             }
+            dst[2 * at] = re;
+            dst[2 * at + 1] = im;
+        } else {
+            dst[at] = (j < sd.L) ? (To)src[sd.src_off + j] : To(0);
         }
     }
 }
 
+// Validity flags (one thread each) and zero outputs of invalid instances
+// (one wave each, lanes along the bins).
 template <typename O>
-__global__ void fill_invalid_kernel(const int32_t* __restrict__ inv, const int64_t* __restrict__ bin_off,
-                                    const int32_t* __restrict__ inst_K, int64_t n_inv, cpx<O>* sp,
-                                    O* pw, const uint8_t* __restrict__ mask, uint8_t* valid,
-                                    int64_t n_inst)
+__global__ __launch_bounds__(kBlock) void fill_invalid_kernel(const int32_t* __restrict__ inv,
+                                                              const int64_t* __restrict__ bin_off,
+                                                              const int32_t* __restrict__ inst_K, int64_t n_inv,
+                                                              cpx<O>* sp, O* pw, const uint8_t* __restrict__ mask,
+                                                              uint8_t* valid, int64_t n_inst)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (valid && i < n_inst) valid[i] = mask[i];
-    if (i < n_inv) {
-        const int32_t ii = inv[i];
+    const int64_t q = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x >> 6);
+    if (q < n_inv) {
+        const int32_t ii = inv[q];
         const int64_t o = bin_off[ii];
-        for (int k = 0; k < inst_K[ii]; ++k) {
+        const int K = inst_K[ii];
+        for (int k = threadIdx.x & 63; k < K; k += kWave) {
             if (sp) sp[o + k] = cpx<O>{O(0), O(0)};
             if (pw) pw[o + k] = O(0);
         }
@@ -1035,11 +1164,15 @@ size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode)
     return b;
 }
 
-hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, const void* strain,
+hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int64_t max_entries, const void* strain,
                                     int strain_fp64, int strain_complex, int dst_fp64, hipStream_t st)
 {
     if (n_segs <= 0) return hipSuccess;
-    dim3 grid((unsigned)n_segs), block(kBlock);
+    // about 16 entries per thread of the largest segment, at most 64 workgroups per segment
+    int64_t gy = (max_entries + kBlock * 16 - 1) / (kBlock * 16);
+    if (gy < 1) gy = 1;
+    if (gy > 64) gy = 64;
+    dim3 grid((unsigned)n_segs, (unsigned)gy), block(kBlock);
     if (strain_fp64 && dst_fp64)
         strain_lane_major_kernel<double, double><<<grid, block, 0, st>>>(segs, (const double*)strain, strain_complex);
     else if (strain_fp64)
@@ -1209,6 +1342,29 @@ hipError_t launch_epilogue_sum(const EpilogueArgs& a, const EpilogueOut& o, int 
     return launch_epi<1>(a, o, fp64, out_fp64, st);
 }
 
+hipError_t launch_rows_sum(const EpilogueArgs& a, const EpilogueOut& o, int out_fp64, hipStream_t st)
+{
+    if (a.tmpl_count <= 0) return hipSuccess;
+    dim3 grid((unsigned)a.tmpl_count), block(kBlock);
+    if (out_fp64)
+        rows_sum_kernel<double><<<grid, block, 0, st>>>(a, o);
+    else
+        rows_sum_kernel<float><<<grid, block, 0, st>>>(a, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_sum_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
+                                 EpilogueOut o, int out_fp64, hipStream_t st)
+{
+    if (blocks <= 0) return hipSuccess;
+    dim3 grid((unsigned)blocks), block(kBlock);
+    if (out_fp64)
+        rows_sum_multi_kernel<double><<<grid, block, 0, st>>>(tab, block_off, ncls, o);
+    else
+        rows_sum_multi_kernel<float><<<grid, block, 0, st>>>(tab, block_off, ncls, o);
+    return hipGetLastError();
+}
+
 hipError_t launch_epilogue_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
                                  int sum_mode, EpilogueOut o, int fp64, int out_fp64, size_t lds, hipStream_t st)
 {
@@ -1228,9 +1384,11 @@ hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,
                                int out_fp64, const uint8_t* mask, uint8_t* valid, int64_t n_inst,
                                hipStream_t st)
 {
-    const int64_t nthreads = n_inv > (valid ? n_inst : 0) ? n_inv : (valid ? n_inst : 0);
-    if (nthreads <= 0) return hipSuccess;
-    dim3 grid((unsigned)((nthreads + 255) / 256)), block(256);
+    const int64_t b_flags = valid ? (n_inst + kBlock - 1) / kBlock : 0;
+    const int64_t b_inv = (n_inv + kBlock / kWave - 1) / (kBlock / kWave);
+    const int64_t blocks = b_flags > b_inv ? b_flags : b_inv;
+    if (blocks <= 0) return hipSuccess;
+    dim3 grid((unsigned)blocks), block(kBlock);
     if (out_fp64)
         fill_invalid_kernel<double><<<grid, block, 0, st>>>(inv_inst, bin_off, inst_K, n_inv,
                                                             (cpx<double>*)spectra, (double*)power,

@@ -101,8 +101,10 @@ struct Class {
     std::vector<int64_t> tmpl_list_off, tmpl_stat_off;
     // device copies
     int flush_period = 16;
+    std::vector<int32_t> entry_seg;    // segment of each template-major list entry
+    int64_t row_base = 0;              // two-pass sum: first element of the class's power rows
     DevBuf d_inst, d_coef, d_taps, d_dec, d_tw, d_phase, d_strain, d_tmpl_id, d_tmpl_list,
-        d_tmpl_list_off, d_tmpl_stat_off;
+        d_tmpl_list_off, d_tmpl_stat_off, d_entry_seg;
 };
 
 // Classes launched together: one kernel instantiation and one LDS
@@ -134,11 +136,20 @@ struct nr_plan_s {
     DevBuf d_points, d_grid, d_mask, d_bin_off, d_inst_K, d_invalid, d_flag;
     // lane-major layout of every class, by destination precision
     std::vector<SegDev> lm_segs[2];
+    int64_t lm_max_entries[2] = {0, 0};
     DevBuf d_lm_segs[2];
     // batched mode: every class in one chunk with its own grid region, the
     // classes launched in groups instead of one after another
     bool batched = false;
+    bool two_pass = false;             // segment sum through power rows (P.d_rows)
+    DevBuf d_rows;
     std::vector<Group> spread_groups, epi_groups;
+    // side streams of a batched plan: independent groups run on them at the
+    // same time, forked from and joined back to the plan's stream by events
+    // (which HIP graph capture records as dependencies)
+    std::vector<hipStream_t> side;
+    hipEvent_t ev_fork[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> ev_join[2];
     int64_t n_invalid = 0;
     int64_t workspace = 0;
     int n_chunks = 0;
@@ -164,6 +175,11 @@ struct nr_plan_s {
             (void)hipEventDestroy(t.b);
         }
         for (auto e : event_pool) (void)hipEventDestroy(e);
+        for (int k = 0; k < 2; ++k) {
+            if (ev_fork[k]) (void)hipEventDestroy(ev_fork[k]);
+            for (auto e : ev_join[k]) (void)hipEventDestroy(e);
+        }
+        for (auto s : side) (void)hipStreamDestroy(s);
     }
 };
 
@@ -315,17 +331,22 @@ int spread_code(int method)
     return method == NR_METHOD_STAGED ? 0 : method == NR_METHOD_CELLRUN ? 2 : 1;
 }
 
-// Rounds of 63 cell runs that one cell-run instance needs: its unwrapped
-// cell index spans about n df dtau(L - 1) cells, plus the two ends.
-int cellrun_rounds(const InstHost& h, int64_t L, int n, double df)
+// Grid cells that one instance's time series visits: its unwrapped cell
+// index spans about n df dtau(L - 1) cells, plus the two ends.
+double cells_visited(const InstHost& h, int64_t L, int n, double df)
 {
     long double span;
     if (h.beta == 0.0)
         span = h.c * (long double)(L - 1);
     else
         span = h.a * (1.0L - powl(1.0L - (long double)h.y_max, 0.625L));
-    const long double cells = (long double)n * (long double)df * span + 2.0L;
-    return (int)std::min<long double>(1e6L, std::ceil(cells / 63.0L));
+    return (double)((long double)n * (long double)df * span + 2.0L);
+}
+
+// Rounds of 63 cell runs that one cell-run instance needs.
+int cellrun_rounds(const InstHost& h, int64_t L, int n, double df)
+{
+    return (int)std::min(1e6, std::ceil(cells_visited(h, L, n, df) / 63.0));
 }
 
 int default_parts(int64_t L)
@@ -335,15 +356,27 @@ int default_parts(int64_t L)
     return 4;
 }
 
-// Waves per cell-run instance: no more than its rounds; up to 16 in plans
-// too small to fill the GPU, else the sample-run rule.
+// Waves per cell-run instance (its rounds are dealt to its waves in turn).
+// Plans too small to fill the GPU: as many as there are rounds, up to 16;
+// otherwise the sample-run rule, keeping at least four rounds per wave.
 int cellrun_parts(int rounds, bool small_plan, int64_t L)
 {
-    const int cap = small_plan ? 16 : default_parts(L);
     int p = 1;
-    while (p * 2 <= std::min(rounds, cap)) p *= 2;
+    if (small_plan) {
+        while (p * 2 <= 16 && p * 2 <= rounds) p *= 2;
+    } else {
+        while (p * 2 <= default_parts(L) && rounds >= 4 * p * 2) p *= 2;
+    }
     return p;
 }
+
+// Automatic spreader: cell runs, unless the time series spends fewer than
+// kCellRunMinDensity samples in each cell it visits AND the spreader's LDS
+// leaves fewer than five workgroups per compute unit (sparse runs pay more
+// for the boundary search and partly used quads than they save, and that
+// search's dependent chain needs resident waves to hide behind).
+constexpr double kCellRunMinDensity = 24.0;
+constexpr size_t kCellRunMaxSparseLds = kLdsBytes / 5;
 
 // Waves per instance when the whole plan has too few waves to fill the chip:
 // enough to bring the samples per lane down to about 64 (at most 16 waves).
@@ -578,6 +611,10 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             ndeg = horner_series(h, f_ref, fp64 ? 1e-14 : 1e-11, series);
         }
         int method = resolve_method(o.method);
+        if (o.method == NR_METHOD_AUTO &&
+            ((double)g.n_samples >= kCellRunMinDensity * cells_visited(h, g.n_samples, n, df_i) ||
+             spread_lds_bytes(fp64, n) <= kCellRunMaxSparseLds))
+            method = NR_METHOD_CELLRUN;
         int parts = o.parts ? o.parts : small_plan ? small_plan_parts(g.n_samples) : default_parts(g.n_samples);
         if (method == NR_METHOD_CELLRUN && o.parts == 0)
             parts = cellrun_parts(cellrun_rounds(h, g.n_samples, n, df_i), small_plan, g.n_samples);
@@ -689,7 +726,11 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         c.pt_entries = pt;
         c.tmpl_list_off.push_back(0);
         for (auto& l : lists) {
-            c.tmpl_list.insert(c.tmpl_list.end(), l.begin(), l.end());
+            for (int32_t k : l) {
+                c.inst[k].entry = (int32_t)c.tmpl_list.size();
+                c.entry_seg.push_back(c.inst[k].seg);
+                c.tmpl_list.push_back(k);
+            }
             c.tmpl_list_off.push_back((int64_t)c.tmpl_list.size());
         }
         // collective flush period: about half the samples a lane spends in one cell
@@ -743,14 +784,17 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         for (SegDev& sd : c.segs) {
             sd.dst = c.d_strain.p;
             P.lm_segs[c.fp64].push_back(sd);
+            P.lm_max_entries[c.fp64] = std::max(P.lm_max_entries[c.fp64], (int64_t)sd.parts * sd.C * kWave);
         }
         c.d_tmpl_id.upload(c.tmpl_id, "templates");
         c.d_tmpl_list.upload(c.tmpl_list, "template lists");
         c.d_tmpl_list_off.upload(c.tmpl_list_off, "template lists");
         c.d_tmpl_stat_off.upload(c.tmpl_stat_off, "template offsets");
+        c.d_entry_seg.upload(c.entry_seg, "list segments");
         P.workspace += (int64_t)(c.d_inst.bytes + c.d_coef.bytes + c.d_strain.bytes +
                                  c.d_phase.bytes + c.d_taps.bytes + c.d_dec.bytes + c.d_tw.bytes + c.d_tmpl_id.bytes +
-                                 c.d_tmpl_list.bytes + c.d_tmpl_list_off.bytes + c.d_tmpl_stat_off.bytes);
+                                 c.d_tmpl_list.bytes + c.d_tmpl_list_off.bytes + c.d_tmpl_stat_off.bytes +
+                                 c.d_entry_seg.bytes);
     }
     if (fixed_bytes + grid_chunk_bytes + point_chunk_bytes > cap)
         fail(NR_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(fixed_bytes + grid_chunk_bytes + point_chunk_bytes) +
@@ -776,12 +820,40 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         grid_chunk_bytes = go;
         point_chunk_bytes = po;
     }
+    // Two-pass segment sum (power rows, then per-template row sums) when
+    // every class fits one chunk and the rows fit the workspace.
+    {
+        int64_t rows = 0;
+        for (auto& cp : P.classes) {
+            cp->row_base = rows;
+            rows += (int64_t)cp->inst.size() * cp->kmax;
+        }
+        const int64_t rbytes = rows * (P.out_fp64 ? 8 : 4);
+        P.two_pass = one_chunk && !P.classes.empty() &&
+                     fixed_bytes + grid_chunk_bytes + point_chunk_bytes + rbytes <= cap;
+        if (P.two_pass) P.d_rows.alloc((size_t)rbytes, "power rows");
+    }
     P.d_grid.alloc((size_t)grid_chunk_bytes, "grid");
     if (point_chunk_bytes > 0) P.d_points.alloc((size_t)point_chunk_bytes, "point stream");
     for (int f = 0; f < 2; ++f) P.d_lm_segs[f].upload(P.lm_segs[f], "segments");
     if (P.batched) {
         build_groups(P);
         P.n_chunks = (int)P.spread_groups.size();
+        const size_t most = std::max(P.spread_groups.size(), P.epi_groups.size());
+        const int n_side = (int)std::min<size_t>(3, most > 0 ? most - 1 : 0);
+        for (int i = 0; i < n_side; ++i) {
+            hipStream_t st;
+            hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "side stream");
+            P.side.push_back(st);
+        }
+        for (int k = 0; k < 2 && n_side > 0; ++k) {
+            hip_check(hipEventCreateWithFlags(&P.ev_fork[k], hipEventDisableTiming), "fork event");
+            for (int i = 0; i < n_side; ++i) {
+                hipEvent_t e;
+                hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "join event");
+                P.ev_join[k].push_back(e);
+            }
+        }
     }
     if (!P.classes.empty()) P.method = P.classes[0]->method;
     P.d_mask.upload(P.valid, "mask");
@@ -793,7 +865,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     P.d_bin_off.upload(P.bin_off, "bin offsets");
     P.d_inst_K.upload(P.inst_K, "bins");
     P.d_flag.alloc(sizeof(int32_t), "flag");
-    P.workspace += (int64_t)(P.d_grid.bytes + P.d_points.bytes + P.d_mask.bytes + P.d_invalid.bytes +
+    P.workspace += (int64_t)(P.d_grid.bytes + P.d_points.bytes + P.d_mask.bytes + P.d_invalid.bytes + P.d_rows.bytes +
                              P.d_lm_segs[0].bytes + P.d_lm_segs[1].bytes +
                              P.d_bin_off.bytes + P.d_inst_K.bytes + P.d_flag.bytes);
 }
@@ -869,6 +941,8 @@ EpilogueArgs epilogue_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     e.tmpl_count = ch.tmpl_count;
     e.slots = grid_slots(c.parts);
     e.kmax = c.kmax;
+    e.row_base = c.row_base;
+    e.entry_seg = (const int32_t*)c.d_entry_seg.p;
     return e;
 }
 
@@ -993,54 +1067,98 @@ void lane_major(nr_plan_s& P, const void* strain)
         if (!P.lm_segs[f].empty())
             timed_launch(P, NR_STAGE_LAYOUT, [&] {
                 return launch_strain_lane_major((const SegDev*)P.d_lm_segs[f].p, (int32_t)P.lm_segs[f].size(),
-                                                strain, P.strain_fp64, P.opt.strain_complex, f, P.stream);
+                                                P.lm_max_entries[f], strain, P.strain_fp64, P.opt.strain_complex,
+                                                f, P.stream);
             }, "strain layout");
 }
 
-// Batched mode: tau for staged classes, then one spread launch per group.
+// Side streams usable for k independent launch sequences (0 when profiling:
+// the stage timers bracket launches on the plan's stream).
+int side_count(const nr_plan_s& P, size_t k)
+{
+    if (P.opt.profile || P.side.empty() || k < 2) return 0;
+    return (int)std::min(P.side.size(), k - 1);
+}
+
+void fork_side(nr_plan_s& P, int which, int n)
+{
+    if (n == 0) return;
+    hip_check(hipEventRecord(P.ev_fork[which], P.stream), "fork");
+    for (int i = 0; i < n; ++i) hip_check(hipStreamWaitEvent(P.side[i], P.ev_fork[which], 0), "fork");
+}
+
+void join_side(nr_plan_s& P, int which, int n)
+{
+    for (int i = 0; i < n; ++i) {
+        hip_check(hipEventRecord(P.ev_join[which][i], P.side[i]), "join");
+        hip_check(hipStreamWaitEvent(P.stream, P.ev_join[which][i], 0), "join");
+    }
+}
+
+// Stream of the i-th of several independent sequences.
+hipStream_t lane_stream(const nr_plan_s& P, size_t i, int n)
+{
+    const size_t r = i % (size_t)(n + 1);
+    return r == 0 ? P.stream : P.side[r - 1];
+}
+
+// Batched mode: per spread group, the tau kernel of its staged classes and
+// then one spread launch; independent groups run on side streams.
 void run_front_batched(nr_plan_s& P)
 {
-    for (auto& cp : P.classes) {
-        Class& c = *cp;
-        if (c.method != NR_METHOD_STAGED || c.chunks.empty()) continue;
-        SpreadArgs a = spread_args(P, c, c.chunks[0]);
-        timed_launch(P, NR_STAGE_TAU, [&] { return launch_tau(a, c.fp64, P.stream); }, "tau kernel");
-    }
-    for (Group& g : P.spread_groups) {
+    const int ns = side_count(P, P.spread_groups.size());
+    fork_side(P, 0, ns);
+    for (size_t gi = 0; gi < P.spread_groups.size(); ++gi) {
+        Group& g = P.spread_groups[gi];
+        hipStream_t st = lane_stream(P, gi, ns);
+        for (int ci : g.cls) {
+            Class& c = *P.classes[ci];
+            if (c.method != NR_METHOD_STAGED || c.chunks.empty()) continue;
+            SpreadArgs a = spread_args(P, c, c.chunks[0]);
+            timed_launch(P, NR_STAGE_TAU, [&] { return launch_tau(a, c.fp64, st); }, "tau kernel");
+        }
         if (g.cls.size() == 1) {
             Class& c = *P.classes[g.cls[0]];
             SpreadArgs a = spread_args(P, c, c.chunks[0]);
-            timed_launch(P, NR_STAGE_SPREAD, [&] { return launch_spread(a, c.fp64, c.deg, g.fused, P.stream); },
+            timed_launch(P, NR_STAGE_SPREAD, [&] { return launch_spread(a, c.fp64, c.deg, g.fused, st); },
                          "spread kernel");
             continue;
         }
         timed_launch(P, NR_STAGE_SPREAD, [&] {
             return launch_spread_multi((const SpreadArgs*)g.d_tab.p, (const int64_t*)g.d_off[0].p, (int)g.cls.size(),
                                        g.blocks[0], g.fp64, g.deg, g.fused, P.opt.strain_complex, g.snap, g.lds[0],
-                                       P.stream);
+                                       st);
         }, "spread kernel");
     }
+    join_side(P, 0, ns);
 }
 
-// Batched mode: one epilogue launch per group (mode 0 spectra, 1 segment sum).
+// Batched mode: one epilogue launch per group (mode 0 spectra, 1 segment
+// sum).  Spectra groups write disjoint bins and run side by side; segment
+// sums of different groups may add into the same templates and stay in order.
 void run_epilogue_batched(nr_plan_s& P, int mode, const EpilogueOut& out)
 {
-    for (Group& g : P.epi_groups) {
+    const int ns = mode ? 0 : side_count(P, P.epi_groups.size());
+    fork_side(P, 1, ns);
+    for (size_t gi = 0; gi < P.epi_groups.size(); ++gi) {
+        Group& g = P.epi_groups[gi];
+        hipStream_t st = lane_stream(P, gi, ns);
         if (g.cls.size() == 1) {
             Class& c = *P.classes[g.cls[0]];
             EpilogueArgs e = epilogue_args(P, c, c.chunks[0]);
             timed_launch(P, NR_STAGE_EPILOGUE, [&] {
-                return mode ? launch_epilogue_sum(e, out, c.fp64, P.out_fp64, P.stream)
-                            : launch_epilogue_spectra(e, out, c.fp64, P.out_fp64, P.stream);
+                return mode ? launch_epilogue_sum(e, out, c.fp64, P.out_fp64, st)
+                            : launch_epilogue_spectra(e, out, c.fp64, P.out_fp64, st);
             }, mode ? "segment sum" : "epilogue");
             continue;
         }
         timed_launch(P, NR_STAGE_EPILOGUE, [&] {
             return launch_epilogue_multi((const EpilogueArgs*)g.d_tab.p, (const int64_t*)g.d_off[mode].p,
                                          (int)g.cls.size(), g.blocks[mode], mode, out, g.fp64, P.out_fp64,
-                                         g.lds[mode], P.stream);
+                                         g.lds[mode], st);
         }, mode ? "segment sum" : "epilogue");
     }
+    join_side(P, 1, ns);
 }
 
 void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* power, uint8_t* valid);
@@ -1143,6 +1261,42 @@ void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, vo
     out.stat = stat;
     out.n_used = n_used;
     lane_major(P, strain);
+    if (P.two_pass) {
+        // first pass: power rows (spectra-mode epilogue); second: row sums
+        EpilogueOut rows{};
+        rows.rows = P.d_rows.p;
+        out.rows = P.d_rows.p;
+        if (P.batched) {
+            run_front_batched(P);
+            run_epilogue_batched(P, 0, rows);
+            for (Group& g : P.epi_groups) {
+                if (g.cls.size() == 1) {
+                    Class& c = *P.classes[g.cls[0]];
+                    EpilogueArgs e = epilogue_args(P, c, c.chunks[0]);
+                    timed_launch(P, NR_STAGE_EPILOGUE, [&] { return launch_rows_sum(e, out, P.out_fp64, P.stream); },
+                                 "segment sum");
+                    continue;
+                }
+                timed_launch(P, NR_STAGE_EPILOGUE, [&] {
+                    return launch_rows_sum_multi((const EpilogueArgs*)g.d_tab.p, (const int64_t*)g.d_off[1].p,
+                                                 (int)g.cls.size(), g.blocks[1], out, P.out_fp64, P.stream);
+                }, "segment sum");
+            }
+            return;
+        }
+        for (auto& cp : P.classes) {
+            Class& c = *cp;
+            for (const Chunk& ch : c.chunks) {
+                run_front(P, c, ch);
+                EpilogueArgs e = epilogue_args(P, c, ch);
+                timed_launch(P, NR_STAGE_EPILOGUE,
+                             [&] { return launch_epilogue_spectra(e, rows, c.fp64, P.out_fp64, P.stream); }, "epilogue");
+                timed_launch(P, NR_STAGE_EPILOGUE, [&] { return launch_rows_sum(e, out, P.out_fp64, P.stream); },
+                             "segment sum");
+            }
+        }
+        return;
+    }
     if (P.batched) {
         run_front_batched(P);
         run_epilogue_batched(P, 1, out);
