@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=768,
+    ap.add_argument("--cpu-sample", type=int, default=3072,
                     help="instances timed on the oracle (seeded sample)")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain copy kernel run once for counter calibration")
@@ -66,6 +66,29 @@ def parse():
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def committed_traffic(kernel_key):
+    """HBM bytes per launch of kernel_key (FETCH_SIZE and WRITE_SIZE scaled by
+    the copy-kernel calibration) from the rocprofv3 summaries under profiles/,
+    or None when none covers it or its kernel sources changed since."""
+    import glob
+    import hashlib
+    import re
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        txt = open(path).read()
+        m = re.search(r"traffic_bytes_per_launch\[(.+?)\]: (\d+)", txt)
+        h = re.search(r"source_sha256: ([0-9a-f]+)", txt)
+        src = re.search(r"sources: (.+)", txt)
+        if not (m and h and src) or m.group(1) != kernel_key:
+            continue
+        digest = hashlib.sha256()
+        for rel in src.group(1).split():
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                digest.update(f.read())
+        if digest.hexdigest() == h.group(1):
+            return float(m.group(2))
+    return None
 
 
 def algorithmic_ops(classes):
@@ -250,10 +273,14 @@ def main():
     elif dom == "spread":
         ops = algorithmic_ops(cls)
         achieved = ops / max(launches, 1) / (per_launch_ms * 1e-3) / 1e12
-        kname = "spread_runs_kernel<float>" if cls[0].method == 3 else "spread_kernel<float, fused>"
+        if cls[0].method == 3:
+            kname = f"nr::spread_runs_kernel<float, {cls[0].degree}, false>"
+        else:
+            kname = f"nr::spread_kernel<float, {cls[0].degree}, true, false, false>"
         roof = {"kernel": kname, "bound": "alu", "achieved": achieved,
                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": None, "ops_per_point": ops / pts}
+                "traffic": committed_traffic(kname) if len(cls) == 1 else None,
+                "traffic_unit": "bytes per launch", "ops_per_point": ops / pts}
     else:
         bytes_step = info.n_valid * n * 8 + info.stat_bins * 8
         achieved = bytes_step / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9

@@ -118,22 +118,32 @@ __device__ __forceinline__ double dtau_of(const TauConsts& t, int j)
 
 // dtau of the four samples j0 .. j0+3 of a quad (series form only): one
 // dispatch on the degree for all four.
+// top: b[N - 1] held in a vector register for the whole loop (a VALU
+// operation may read only one scalar operand, so starting each Horner
+// chain from it saves a move per sample).
 template <int N>
-__device__ __forceinline__ void horner4(const double* b, int j0, double* out)
+__device__ __forceinline__ void horner4(const double* b, double top, double jd0, double* out)
 {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) out[e] = horner<N>(b, (double)(j0 + e));
+    for (int e = 0; e < 4; ++e) {
+        const double x = jd0 + (double)e;
+        double acc = top;
+#pragma unroll
+        for (int k = N - 2; k >= 0; --k) acc = fma(acc, x, b[k]);
+        out[e] = acc * x;
+    }
 }
 
-__device__ __forceinline__ void dtau4(const TauConsts& t, int j0, double* out)
+__device__ __forceinline__ void dtau4(const TauConsts& t, double top, int j0, double* out)
 {
+    const double jd0 = (double)j0;
     switch (t.ndeg) {
     case 0:
 #pragma unroll
-        for (int e = 0; e < 4; ++e) out[e] = (double)(j0 + e) * t.c;
+        for (int e = 0; e < 4; ++e) out[e] = (jd0 + (double)e) * t.c;
         return;
 #define NR_H4(N) \
-    case N: horner4<N>(t.bc, j0, out); return;
+    case N: horner4<N>(t.bc, top, jd0, out); return;
         NR_H4(1) NR_H4(2) NR_H4(3) NR_H4(4) NR_H4(5) NR_H4(6) NR_H4(7) NR_H4(8) NR_H4(9) NR_H4(10)
         NR_H4(11) NR_H4(12) NR_H4(13) NR_H4(14) NR_H4(15) NR_H4(16)
 #undef NR_H4
@@ -645,6 +655,9 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
         // per-sample scales: grid position in cells and phase in table steps
         const double dfn = tc.df * nd, hnn = tc.hn * nd;
         const double fcs = tc.fc * (double)(1 << PhaseTable<T>::bits);
+        // leading series coefficient, kept in a vector register
+        double top = tc.ndeg > 0 ? tc.b[tc.ndeg - 1] : 0.0;
+        asm volatile("" : "+v"(top));
         for (int r = part; r < rounds; r += parts) {
             const double t = U0 + 63.0 * r + (double)lane;
             const int js = first_at_least(tc, L, t, nd);
@@ -657,7 +670,7 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
             for (int q = js & ~3; q < je; q += 4) {
                 const Quad<E> xq = *reinterpret_cast<const Quad<E>*>(xs + q);
                 double dt[4];
-                dtau4(tc, q, dt);
+                dtau4(tc, top, q, dt);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int j = q + e;
@@ -827,6 +840,27 @@ __device__ __forceinline__ void team_sync(int ts)
 // to (j / Ns) Ns R + k + q Ns.  tw is the LDS copy of exp(-2 pi i t / n).
 // Every lane of the workgroup runs every pass.  Returns the buffer holding
 // the result.
+// One pass of radix R (a compile-time constant, so the R values of a
+// butterfly stay in registers).
+template <typename T, int R>
+__device__ __forceinline__ void fft_pass(const cpx<T>* src, cpx<T>* dst, const cpx<T>* tw, int n, int Ns, int tid,
+                                         int ts)
+{
+    const int nb = n / R;
+    const int twstep = n / (Ns * R);
+    for (int j = tid; j < nb; j += ts) {
+        const int k = j % Ns;
+        cpx<T> v[R];
+        v[0] = src[j];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(src[j + r * nb], tw[r * k * twstep]);
+        dft_small(v, R);
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
+    }
+}
+
 template <typename T>
 __device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* tw, const FftPlanDev& fp, int tid, int ts)
 {
@@ -834,18 +868,14 @@ __device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* tw, const FftPlanDev& fp,
     cpx<T>* src = buf;
     cpx<T>* dst = buf + n;
     int Ns = 1;
-    for (int p = 0; p < fp.nr; ++p) {
+    const int nr = fp.nr;
+    for (int p = 0; p < nr; ++p) {
         const int R = fp.radix[p];
-        const int nb = n / R;
-        const int twstep = n / (Ns * R);
-        for (int j = tid; j < nb; j += ts) {
-            const int k = j % Ns;
-            cpx<T> v[5];
-            v[0] = src[j];
-            for (int r = 1; r < R; ++r) v[r] = cmul(src[j + r * nb], tw[r * k * twstep]);
-            dft_small(v, R);
-            const int base = (j / Ns) * Ns * R + k;
-            for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
+        switch (R) {
+        case 2: fft_pass<T, 2>(src, dst, tw, n, Ns, tid, ts); break;
+        case 3: fft_pass<T, 3>(src, dst, tw, n, Ns, tid, ts); break;
+        case 4: fft_pass<T, 4>(src, dst, tw, n, Ns, tid, ts); break;
+        default: fft_pass<T, 5>(src, dst, tw, n, Ns, tid, ts); break;
         }
         team_sync(ts);
         cpx<T>* t = src;
@@ -968,7 +998,7 @@ __global__ __launch_bounds__(kBlock) void rows_sum_multi_kernel(const EpilogueAr
                                                                 EpilogueOut o)
 {
     const int c = class_of_block(block_off, ncls, blockIdx.x);
-    const EpilogueArgs a = tab[c];
+    const EpilogueArgs& a = tab[c];  // read in place: a private copy would spill the radix list
     rows_sum_block<O>(a, o, (int64_t)blockIdx.x - block_off[c]);
 }
 
@@ -1061,7 +1091,7 @@ __global__ __launch_bounds__(kBlock) void epilogue_multi_kernel(const EpilogueAr
                                                                 int ncls, EpilogueOut o)
 {
     const int c = class_of_block(block_off, ncls, blockIdx.x);
-    const EpilogueArgs a = tab[c];
+    const EpilogueArgs& a = tab[c];  // read in place: a private copy would spill the radix list
     const int64_t lb = (int64_t)blockIdx.x - block_off[c];
     if (SUM)
         epilogue_sum_block<T, O>(a, o, lb);
