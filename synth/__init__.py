@@ -329,18 +329,28 @@ def beta_bank(n_beta=69, beta_lo=3e-8, beta_hi=7e-4, f0=50.0):
     return betas, (betas / c) ** 0.6
 
 
-def paper_bank(hours=1.0, seed=5, fs=512.0, t_coh=30.0, n_beta=69):
-    """The paper's coherent workload (Sec. VI): 30 s segments resampled at 512 Hz,
-    69 beta templates uniform over [3e-8, 7e-4] at f0 = 50 Hz, the full 40-60 Hz
-    band as 600 bins of 1/30 Hz; N(0,1) noise (no injection)."""
+def paper_bank(hours=1.0, seed=5, fs=512.0, t_coh=30.0, n_beta=69, inject=None):
+    """The paper's coherent workload (Sec. III.A, VI): 30 s segments at 512 Hz,
+    each resampled with every one of 69 beta templates (uniform over
+    [3e-8, 7e-4], beta(f0 = 50 Hz, Mc)) referenced at the segment's own start,
+    and transformed onto the full 40-60 Hz band in bins of 1/T_coh (600 at
+    30 s).  N(0,1) noise; inject = (Mc, t0, amplitude, phi0) adds a 0PN chirp
+    that passes 40 Hz at time t0 (stops at 0.45 fs).  Every segment has
+    seg_t = 0: its own start is the resampling reference."""
     L = int(round(t_coh * fs))
     n_seg = int(round(hours * 3600.0 / t_coh))
     rng = np.random.default_rng(seed)
     x = rng.standard_normal(n_seg * L)
-    off, ln, fsa, ts = _segments(n_seg, L, fs)
+    if inject is not None:
+        mc_i, t0_i, amp, ph = inject
+        t = np.arange(n_seg * L) / fs
+        x = x + injection(t, BAND_LO, mc_i, amp, t0=t0_i, phi0=ph, f_stop=0.45 * fs)
+    off, ln, fsa, _ = _segments(n_seg, L, fs)
     _, mc = beta_bank(n_beta)
     m = len(mc)
-    return Workload(name=f"paper_beta_bank_{hours:g}h_{n_beta}beta_512Hz", strain=x,
-                    seg_offset=off, seg_len=ln, seg_fs=fsa, seg_t=ts,
+    K = int(round((BAND_HI - BAND_LO) * t_coh))
+    return Workload(name=f"paper_beta_bank_{hours:g}h_{n_beta}beta_{fs:g}Hz", strain=x,
+                    seg_offset=off, seg_len=ln, seg_fs=fsa, seg_t=np.zeros(n_seg),
                     mc=mc, f0=np.full(m, 50.0), f_lo=np.full(m, BAND_LO), df=np.full(m, 1.0 / t_coh),
-                    n_bins=np.full(m, 600, np.int32), f_max=np.zeros(m), tol=1e-6)
+                    n_bins=np.full(m, K, np.int32), f_max=np.zeros(m), tol=1e-6,
+                    meta={"t_coh": t_coh, "inject": inject})
