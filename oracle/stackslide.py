@@ -31,6 +31,21 @@ import numpy as np
 from . import beta as _beta
 
 
+def _segment(b0, dt, betas, f_lo, df, n_bins, f_start, f_max):
+    """(k, j, f) of a segment dt after t0, or None once the track has ended."""
+    u = 1.0 - (8.0 / 3.0) * b0 * dt
+    if not u > 0.0:
+        return None
+    f = f_start * u ** (-3.0 / 8.0)
+    if f > f_max:
+        return None
+    j = math.floor((f - f_lo) / df + 0.5)
+    if j < 0 or j >= n_bins:
+        return None
+    k = int(np.argmin(np.abs(betas - b0 / u)))       # first minimum: the lower index on a tie
+    return k, j, f
+
+
 def track(mc, t0, n_seg, t_coh, betas, f_lo, df, n_bins, f_start, f_max):
     """Segments of one track: list of (i, k, j, f_i) in segment order."""
     b0 = _beta(mc, f_start)
@@ -40,18 +55,24 @@ def track(mc, t0, n_seg, t_coh, betas, f_lo, df, n_bins, f_start, f_max):
         ti = i * t_coh
         if ti < t0:
             continue
-        u = 1.0 - (8.0 / 3.0) * b0 * (ti - t0)
-        if not u > 0.0:
+        r = _segment(b0, ti - t0, betas, f_lo, df, n_bins, f_start, f_max)
+        if r is None:
             break
-        f = f_start * u ** (-3.0 / 8.0)
-        if f > f_max:
+        out.append((i,) + r)
+    return out
+
+
+def track_grid(mc, i0, s, t0_steps, n_seg, t_coh, betas, f_lo, df, n_bins, f_start, f_max):
+    """The track with t0 = (i0 - s / S) t_coh, with segment i0 + m at
+    t_i - t0 = (m + s / S) t_coh (the grid form of the same times)."""
+    b0 = _beta(mc, f_start)
+    betas = np.asarray(betas, dtype=np.float64)
+    out = []
+    for m in range(n_seg - i0):
+        r = _segment(b0, (m + s / t0_steps) * t_coh, betas, f_lo, df, n_bins, f_start, f_max)
+        if r is None:
             break
-        j = math.floor((f - f_lo) / df + 0.5)
-        if j < 0 or j >= n_bins:
-            break
-        bi = b0 / u
-        k = int(np.argmin(np.abs(betas - bi)))      # first minimum: the lower index on a tie
-        out.append((i, k, j, f))
+        out.append((i0 + m,) + r)
     return out
 
 
@@ -84,8 +105,7 @@ def n_sigma(power_kij, mcs, t0_steps, t_coh, betas, f_lo, df, f_start, f_max, no
     if tracks is None:
         tracks = [(c, i0, s) for c in range(len(mcs)) for i0 in range(n_seg) for s in range(t0_steps)]
     for (c, i0, s) in tracks:
-        t0 = (i0 - s / t0_steps) * t_coh
-        segs = track(mcs[c], t0, n_seg, t_coh, betas, f_lo, df, n_bins, f_start, f_max)
+        segs = track_grid(mcs[c], i0, s, t0_steps, n_seg, t_coh, betas, f_lo, df, n_bins, f_start, f_max)
         out[c, i0 * t0_steps + s] = n_sigma_one(P, segs, norm, mu, sigma)
         cnt[c, i0 * t0_steps + s] = len(segs)
     return out, cnt

@@ -354,3 +354,15 @@ def paper_bank(hours=1.0, seed=5, fs=512.0, t_coh=30.0, n_beta=69, inject=None):
                     mc=mc, f0=np.full(m, 50.0), f_lo=np.full(m, BAND_LO), df=np.full(m, 1.0 / t_coh),
                     n_bins=np.full(m, K, np.int32), f_max=np.zeros(m), tol=1e-6,
                     meta={"t_coh": t_coh, "inject": inject})
+
+
+def noise_power(n_beta, n_seg, n_bins, L, seed=0, excess=None):
+    """Stand-in stored spectra for the stack-slide: |X|^2 of white N(0,1) noise
+    over L samples (L/2 times a chi^2_2 variate), float32 [n_beta][n_seg][n_bins].
+    excess: optional list of (k, i, j, value) cells set to value."""
+    rng = np.random.default_rng(seed)
+    p = (0.5 * L) * rng.chisquare(2.0, size=(n_beta, n_seg, n_bins))
+    if excess:
+        for (k, i, j, v) in excess:
+            p[k, i, j] = v
+    return p.astype(np.float32)

@@ -29,7 +29,7 @@ def declared_functions():
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         for m in re.finditer(r"\b([a-z_][a-z0-9_]*)\s*\(", src):
             name = m.group(1)
-            if name.startswith(("nufft_resample_", "nr_mlp_")):
+            if name.startswith(("nufft_resample_", "nr_mlp_", "nr_ss_")):
                 names.add(name)
     return names
 
@@ -38,6 +38,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     lib = ctypes.CDLL(nr.LIB_PATH)
     names = declared_functions()
     assert "nufft_resample_plan" in names and "nufft_resample_execute" in names
+    assert "nr_ss_create" in names and "nr_mlp_create" in names
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
@@ -146,3 +147,49 @@ def test_kernel_fourier_transform_matches_adaptive_quadrature(w):
 def test_chirp_beta_matches_oracle():
     for mc, f0 in [(5e-4, 40.0), (1e-2, 50.0), (1e-1, 60.0), (3e-3, 41.5)]:
         assert pkg.nufft_resample_chirp_beta(mc, f0) == pytest.approx(oracle.beta(mc, f0), rel=1e-15)
+
+
+# ------------------------------------------------------------- stack-slide --
+
+def _ss_geom(**kw):
+    from paper_2609_12476_amd import stackslide as ss
+    g = ss.geometry(n_seg=8, n_beta=3, n_bins=600, t_coh=30.0, f_lo=40.0, df=1 / 30, f_start=40.0,
+                    f_max=60.0, norm=2.0 / 15360)
+    for k, v in kw.items():
+        setattr(g, k, v)
+    return g
+
+
+@pytest.mark.parametrize("case", ["n_seg", "layout", "t_coh", "f_max", "sigma", "bank_order", "bank_sign",
+                                  "mc", "steps", "n_mc"])
+def test_stackslide_rejects_bad_arguments(case):
+    """nr_ss_create validates every bound before it touches a device."""
+    from paper_2609_12476_amd import stackslide as ss
+    bank, mc, steps, g = [1e-5, 2e-5, 3e-5], [1e-2, 2e-2], 4, _ss_geom()
+    if case == "n_seg":
+        g = _ss_geom(n_seg=0)
+    elif case == "layout":
+        g = _ss_geom(layout=2)
+    elif case == "t_coh":
+        g = _ss_geom(t_coh=float("nan"))
+    elif case == "f_max":
+        g = _ss_geom(f_max=40.0)
+    elif case == "sigma":
+        g = _ss_geom(sigma=0.0)
+    elif case == "bank_order":
+        bank = [2e-5, 1e-5, 3e-5]
+    elif case == "bank_sign":
+        bank = [-1e-5, 2e-5, 3e-5]
+    elif case == "mc":
+        mc = [1e-2, 0.0]
+    elif case == "steps":
+        steps = 65
+    h = ctypes.c_void_p()
+    lib = ss.lib()
+    b = np.ascontiguousarray(bank, np.float64)
+    m = np.ascontiguousarray(mc, np.float64)
+    n_mc = 0 if case == "n_mc" else len(m)
+    code = lib.nr_ss_create(ctypes.byref(h), ctypes.byref(g), b.ctypes.data, m.ctypes.data, n_mc, steps, None)
+    assert code == nr.NR_ERR_INVALID_ARG
+    assert not h.value
+    assert lib.nr_ss_last_error(None)
