@@ -29,7 +29,7 @@ def declared_functions():
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         for m in re.finditer(r"\b([a-z_][a-z0-9_]*)\s*\(", src):
             name = m.group(1)
-            if name.startswith(("nufft_resample_", "nr_mlp_", "nr_ss_")):
+            if name.startswith(("nufft_resample_", "nr_mlp_", "nr_ss_", "nr_strobo_")):
                 names.add(name)
     return names
 
