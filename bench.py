@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--hours", type=float, default=1.0)
     ap.add_argument("--n-mc", type=int, default=64)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3072,
@@ -523,6 +524,31 @@ def main():
         out["speedup_vs_fp64"] = value / v64
         out["fp64_stage_ms_per_step"] = {k: v[0] / max(3, args.steps // 2) for k, v in st64.items()}
         p64.close()
+
+    # the GPU direct non-uniform DFT (no spreading, no FFT) on the same input
+    if not args.no_direct:
+        log("timing direct-sum baseline")
+        pd = Plan.from_workload(w32, tol=1e-6, precision="fp32", method="direct", profile=True)
+        sd = torch.zeros(pd.info.stat_bins, dtype=torch.float32, device=dev)
+        ud = torch.zeros(pd.n_tmpls, dtype=torch.int32, device=dev)
+        nd_steps = max(2, args.steps // 5)
+        eld, _ = time_steps(pd, x32, sd, ud, nd_steps, 1)
+        sd.zero_()
+        ud.zero_()
+        pd.semicoherent_sum(x32, None, sd, ud)
+        stat.zero_()
+        used.zero_()
+        plan.semicoherent_sum(x32, None, stat, used)
+        torch.cuda.synchronize()
+        sa = stat.double().view(-1, 30)
+        sb = sd.double().view(-1, 30)
+        keep = used > 0
+        dst = (torch.linalg.vector_norm(sa - sb, dim=1)[keep] / torch.linalg.vector_norm(sb, dim=1)[keep]).max()
+        vd = pd.info.n_valid * nd_steps / eld
+        out["direct_baseline"] = {"value": vd, "unit": "spectra/s", "ms_per_step": eld / nd_steps * 1e3,
+                                  "nufft_speedup": value / vd, "stat_rel_l2_max_vs_nufft": float(dst),
+                                  "kind": "GPU direct non-uniform DFT, FP32, same input and outputs"}
+        pd.close()
 
     # oracle on a bounded seeded sample of instances, on the host cores
     if not args.no_cpu_baseline:

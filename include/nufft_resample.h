@@ -85,10 +85,14 @@ typedef enum {
     NR_METHOD_STAGED = 1, /* tau kernel writes a point stream; spreader reads it */
     NR_METHOD_FUSED = 2,  /* the spreader evaluates tau itself; no point stream; each
                              lane takes a fixed run of consecutive samples */
-    NR_METHOD_CELLRUN = 3 /* fused; each lane takes the samples of one visit of the
+    NR_METHOD_CELLRUN = 3, /* fused; each lane takes the samples of one visit of the
                              time series to one grid cell (found by binary search on
                              the monotone cell index), so lanes never change cell
                              inside a run and flush together */
+    NR_METHOD_DIRECT = 4  /* baseline: the plain non-uniform DFT on the GPU, every
+                             (sample, bin) term, no spreading and no FFT; never
+                             chosen automatically; its segment sums need the plan's
+                             power rows to fit the workspace */
 } nr_method;
 
 /* One segment of uniformly sampled strain (Sec. III: T_obs split into T_coh segments). */

@@ -131,6 +131,10 @@ hipError_t launch_epilogue_multi(const EpilogueArgs* tab, const int64_t* block_o
                                  int out_fp64, size_t lds, hipStream_t st);
 int64_t epilogue_blocks(const EpilogueArgs& a, int sum_mode);
 hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st);
+// The direct non-uniform DFT baseline: mode 0 writes spectra/power at the
+// instances' bin offsets, mode 1 power rows for the two-pass segment sum.
+hipError_t launch_direct(const SpreadArgs& a, const EpilogueArgs& e, const EpilogueOut& o, int mode, int fp64,
+                         int out_fp64, hipStream_t st);
 // fused: 0 staged (reads the point stream), 1 fused sample runs, 2 fused cell runs.
 hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st);
 hipError_t launch_epilogue_spectra(const EpilogueArgs& a, const EpilogueOut& out, int fp64,

@@ -1099,6 +1099,121 @@ __global__ __launch_bounds__(kBlock) void epilogue_multi_kernel(const EpilogueAr
         epilogue_spectra_block<T, O>(a, o, lb);
 }
 
+// ------------------------------------------------------- direct baseline --
+//
+// The plain non-uniform DFT X_k = sum_j x_j exp(-2 pi i f_k dtau_j) on the
+// GPU, with no spreading and no FFT: the baseline the NUFFT is measured
+// against.  One wave per instance, lanes over samples (coalesced reads of a
+// plain copy); per sample the phase of the first bin and the step between
+// bins are reduced modulo one cycle in FP64, and the K bins follow by complex
+// rotation in the class precision, 16 bins per pass as four interleaved
+// rotation chains (steps of r^4) so that consecutive rotations do not wait
+// on each other.  The lanes' partial sums are combined by a butterfly of
+// lane exchanges.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <typename T, bool CPLX>
+__device__ __forceinline__ void direct_block(const SpreadArgs& a, const EpilogueArgs& e, const EpilogueOut& o,
+                                             int mode, int out_fp64)
+{
+    constexpr int KB = 16;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+    if (item >= a.count) return;  // whole waves; no barriers below
+    const InstDev d = a.inst[a.first + item];
+    TauConsts tc;
+    load_tau(tc, d, a.coef, 0.0);
+    using E = typename std::conditional<CPLX, cpx<T>, T>::type;
+    const E* __restrict__ xs = reinterpret_cast<const E*>(a.strain_lm) + d.strain_off;
+    const double f_lo = d.fc - (double)d.m0 * d.df;
+    for (int k0 = 0; k0 < d.K; k0 += KB) {
+        T ar[KB], ai[KB];
+#pragma unroll
+        for (int q = 0; q < KB; ++q) ar[q] = ai[q] = T(0);
+        const double f0 = f_lo + (double)k0 * d.df;
+        for (int j = lane; j < d.L; j += kWave) {
+            const double dt = dtau_of<false>(tc, j);
+            const double p0 = __builtin_amdgcn_fract(f0 * dt);
+            const double ps = __builtin_amdgcn_fract(d.df * dt);
+            T s0, c0, s1, c1;
+            if constexpr (sizeof(T) == 4) {
+                sincospif((float)(2.0 * p0), &s0, &c0);
+                sincospif((float)(2.0 * ps), &s1, &c1);
+            } else {
+                sincospi(2.0 * p0, &s0, &c0);
+                sincospi(2.0 * ps, &s1, &c1);
+            }
+            // e_q = x exp(-i 2 pi (p0 + q ps)); r = exp(-i 2 pi ps) = (c1, -s1)
+            T er[4], ei[4];
+            if constexpr (CPLX) {
+                const cpx<T> x = xs[j];
+                er[0] = x.x * c0 + x.y * s0;
+                ei[0] = x.y * c0 - x.x * s0;
+            } else {
+                const T x = xs[j];
+                er[0] = x * c0;
+                ei[0] = -x * s0;
+            }
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                er[q] = er[q - 1] * c1 + ei[q - 1] * s1;
+                ei[q] = ei[q - 1] * c1 - er[q - 1] * s1;
+            }
+            // r^4 = exp(-i 8 pi ps)
+            const T c2 = c1 * c1 - s1 * s1, s2 = T(2) * c1 * s1;
+            const T c4 = c2 * c2 - s2 * s2, s4 = T(2) * c2 * s2;
+#pragma unroll
+            for (int q = 0; q < KB; q += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    ar[q + u] += er[u];
+                    ai[q + u] += ei[u];
+                    const T nr = er[u] * c4 + ei[u] * s4;
+                    ei[u] = ei[u] * c4 - er[u] * s4;
+                    er[u] = nr;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KB; ++q) {
+            ar[q] = wave_sum(ar[q]);
+            ai[q] = wave_sum(ai[q]);
+        }
+        if (lane == 0) {
+            for (int q = 0; q < KB && k0 + q < d.K; ++q) {
+                const int k = k0 + q;
+                const double pw = (double)ar[q] * (double)ar[q] + (double)ai[q] * (double)ai[q];
+                if (mode == 0) {
+                    if (out_fp64) {
+                        if (o.spectra) reinterpret_cast<cpx<double>*>(o.spectra)[d.bin_off + k] = {(double)ar[q], (double)ai[q]};
+                        if (o.power) reinterpret_cast<double*>(o.power)[d.bin_off + k] = pw;
+                    } else {
+                        if (o.spectra) reinterpret_cast<cpx<float>*>(o.spectra)[d.bin_off + k] = {(float)ar[q], (float)ai[q]};
+                        if (o.power) reinterpret_cast<float*>(o.power)[d.bin_off + k] = (float)pw;
+                    }
+                } else {
+                    const int64_t r = e.row_base + (int64_t)d.entry * e.kmax + k;
+                    if (out_fp64) reinterpret_cast<double*>(o.rows)[r] = pw;
+                    else reinterpret_cast<float*>(o.rows)[r] = (float)pw;
+                }
+            }
+        }
+    }
+}
+
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(kBlock) void direct_kernel(SpreadArgs a, EpilogueArgs e, EpilogueOut o, int mode,
+                                                        int out_fp64)
+{
+    direct_block<T, CPLX>(a, e, o, mode, out_fp64);
+}
+
 // ------------------------------------------------------------ utilities --
 
 // Lane-major copies: blockIdx.x picks the class segment, blockIdx.y and the
@@ -1211,6 +1326,21 @@ hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int64_t 
         strain_lane_major_kernel<float, double><<<grid, block, 0, st>>>(segs, (const float*)strain, strain_complex);
     else
         strain_lane_major_kernel<float, float><<<grid, block, 0, st>>>(segs, (const float*)strain, strain_complex);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct(const SpreadArgs& a, const EpilogueArgs& e, const EpilogueOut& o, int mode, int fp64,
+                         int out_fp64, hipStream_t st)
+{
+    if (a.count <= 0) return hipSuccess;
+    dim3 grid((unsigned)((a.count + 3) / 4)), block(kBlock);
+    if (fp64) {
+        if (a.strain_complex) direct_kernel<double, true><<<grid, block, 0, st>>>(a, e, o, mode, out_fp64);
+        else direct_kernel<double, false><<<grid, block, 0, st>>>(a, e, o, mode, out_fp64);
+    } else {
+        if (a.strain_complex) direct_kernel<float, true><<<grid, block, 0, st>>>(a, e, o, mode, out_fp64);
+        else direct_kernel<float, false><<<grid, block, 0, st>>>(a, e, o, mode, out_fp64);
+    }
     return hipGetLastError();
 }
 

@@ -196,7 +196,7 @@ void validate(const nr_segment* segs, int32_t n_segs, const nr_template* tmpls, 
     if (!tmpls || n_tmpls <= 0) fail(NR_ERR_INVALID_ARG, "n_tmpls must be >= 1 with a template array");
     if (!(tol > 0.0 && tol <= 0.1) || !finite(tol)) fail(NR_ERR_INVALID_ARG, "tol must be in (0, 0.1]");
     if (o.precision < NR_FP32 || o.precision > NR_AUTO) fail(NR_ERR_INVALID_ARG, "unknown precision");
-    if (o.method < NR_METHOD_AUTO || o.method > NR_METHOD_CELLRUN) fail(NR_ERR_INVALID_ARG, "unknown method");
+    if (o.method < NR_METHOD_AUTO || o.method > NR_METHOD_DIRECT) fail(NR_ERR_INVALID_ARG, "unknown method");
     if (o.sigma > 0.0 && !(o.sigma >= 1.25 && o.sigma <= 4.0))
         fail(NR_ERR_INVALID_ARG, "sigma must be in [1.25, 4]");
     if (o.parts != 0 && o.parts != 1 && o.parts != 2 && o.parts != 4 && o.parts != 8 && o.parts != 16)
@@ -627,8 +627,9 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             flush = tu.flush;
             snap = tu.snap;
         }
-        // the fused spreaders carry only the series form of tau; instances
-        // that need log1p/expm1 get their points from the tau kernel
+        // the fused spreaders and the direct baseline carry only the series
+        // form of tau; instances that need log1p/expm1 get their points from
+        // the tau kernel
         if (ndeg < 0) method = NR_METHOD_STAGED;
         if (method == NR_METHOD_CELLRUN) snap = 0;  // moments restart with every run
         ClassKey key{fp64, w, n, parts, method, flush, snap};
@@ -665,8 +666,9 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         d.m0 = K / 2;
         d.fc = t.f_lo + (double)d.m0 * df;
         d.L = (int32_t)g.n_samples;
-        // cell runs read a plain copy of the segment (lane-major layout with C = 1)
-        d.C = method == NR_METHOD_CELLRUN
+        // cell runs and the direct baseline read a plain copy of the segment
+        // (lane-major layout with C = 1)
+        d.C = (method == NR_METHOD_CELLRUN || method == NR_METHOD_DIRECT)
                   ? 1
                   : (int32_t)((g.n_samples + (int64_t)kWave * parts - 1) / ((int64_t)kWave * parts));
         d.K = K;
@@ -705,7 +707,9 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
                 sd.dst_off = c.strain_entries;
                 sd.L = d.L;
                 sd.C = d.C;
-                sd.parts = c.method == NR_METHOD_CELLRUN ? (int32_t)((d.L + kWave - 1) / kWave) : c.parts;
+                sd.parts = (c.method == NR_METHOD_CELLRUN || c.method == NR_METHOD_DIRECT)
+                               ? (int32_t)((d.L + kWave - 1) / kWave)
+                               : c.parts;
                 c.segs.push_back(sd);
                 seg_at[d.seg] = sd.dst_off;
                 c.strain_entries += (int64_t)sd.parts * d.C * kWave;
@@ -751,7 +755,9 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             for (int32_t k : lists[t]) ct_of[k] = (int32_t)t;
         fixed_bytes += c.strain_entries * esize;
         // chunks bounded by the workspace cap
-        const int64_t gsize = (int64_t)c.n * (c.fp64 ? 16 : 8) * grid_slots(c.parts);
+        // the direct baseline needs no grid
+        const int64_t gsize =
+            c.method == NR_METHOD_DIRECT ? 0 : (int64_t)c.n * (c.fp64 ? 16 : 8) * grid_slots(c.parts);
         const int64_t psz = c.method == NR_METHOD_STAGED ? (c.fp64 ? psize_d : psize_f) : 0;
         const int64_t budget = std::max<int64_t>(cap / 2, 1);
         int64_t k0 = 0;
@@ -800,9 +806,12 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         fail(NR_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(fixed_bytes + grid_chunk_bytes + point_chunk_bytes) +
                                        " bytes exceeds max_workspace_bytes " + std::to_string(cap));
     // Batched mode when every class fits one chunk and all grids fit together.
-    bool one_chunk = true;
-    for (auto& cp : P.classes) one_chunk = one_chunk && cp->chunks.size() <= 1;
-    P.batched = P.classes.size() > 1 && one_chunk && fixed_bytes + grid_total + point_total <= cap &&
+    bool one_chunk = true, any_direct = false;
+    for (auto& cp : P.classes) {
+        one_chunk = one_chunk && cp->chunks.size() <= 1;
+        any_direct = any_direct || cp->method == NR_METHOD_DIRECT;
+    }
+    P.batched = P.classes.size() > 1 && one_chunk && !any_direct && fixed_bytes + grid_total + point_total <= cap &&
                 grid_total + point_total <= std::max<int64_t>(cap / 2, 1);
     if (P.batched) {
         int64_t go = 0, po = 0;
@@ -832,6 +841,9 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         P.two_pass = one_chunk && !P.classes.empty() &&
                      fixed_bytes + grid_chunk_bytes + point_chunk_bytes + rbytes <= cap;
         if (P.two_pass) P.d_rows.alloc((size_t)rbytes, "power rows");
+        if (any_direct && !P.two_pass)
+            fail(NR_ERR_OUT_OF_MEMORY, "the direct method needs every class in one chunk with its power rows "
+                                       "inside max_workspace_bytes");
     }
     P.d_grid.alloc((size_t)grid_chunk_bytes, "grid");
     if (point_chunk_bytes > 0) P.d_points.alloc((size_t)point_chunk_bytes, "point stream");
@@ -1227,8 +1239,16 @@ void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* pow
         for (auto& cp : P.classes) {
             Class& c = *cp;
             for (const Chunk& ch : c.chunks) {
-                run_front(P, c, ch);
                 EpilogueArgs e = epilogue_args(P, c, ch);
+                if (c.method == NR_METHOD_DIRECT) {
+                    SpreadArgs a = spread_args(P, c, ch);
+                    if (spectra || power)
+                        timed_launch(P, NR_STAGE_SPREAD, [&] {
+                            return launch_direct(a, e, out, 0, c.fp64, P.out_fp64, P.stream);
+                        }, "direct sum");
+                    continue;
+                }
+                run_front(P, c, ch);
                 if (spectra || power)
                     timed_launch(P, NR_STAGE_EPILOGUE,
                                  [&] { return launch_epilogue_spectra(e, out, c.fp64, P.out_fp64, P.stream); },
@@ -1287,10 +1307,18 @@ void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, vo
         for (auto& cp : P.classes) {
             Class& c = *cp;
             for (const Chunk& ch : c.chunks) {
-                run_front(P, c, ch);
                 EpilogueArgs e = epilogue_args(P, c, ch);
-                timed_launch(P, NR_STAGE_EPILOGUE,
-                             [&] { return launch_epilogue_spectra(e, rows, c.fp64, P.out_fp64, P.stream); }, "epilogue");
+                if (c.method == NR_METHOD_DIRECT) {
+                    SpreadArgs a = spread_args(P, c, ch);
+                    timed_launch(P, NR_STAGE_SPREAD, [&] {
+                        return launch_direct(a, e, rows, 1, c.fp64, P.out_fp64, P.stream);
+                    }, "direct sum");
+                } else {
+                    run_front(P, c, ch);
+                    timed_launch(P, NR_STAGE_EPILOGUE,
+                                 [&] { return launch_epilogue_spectra(e, rows, c.fp64, P.out_fp64, P.stream); },
+                                 "epilogue");
+                }
                 timed_launch(P, NR_STAGE_EPILOGUE, [&] { return launch_rows_sum(e, out, P.out_fp64, P.stream); },
                              "segment sum");
             }

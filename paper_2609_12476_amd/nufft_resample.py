@@ -19,11 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libnufft_resample.so")
 NR_OK, NR_ERR_INVALID_ARG, NR_ERR_TOL_UNATTAINABLE, NR_ERR_OUT_OF_MEMORY, NR_ERR_DEVICE, \
     NR_ERR_NONFINITE_INPUT = range(6)
 NR_FP32, NR_FP64, NR_AUTO = 0, 1, 2
-NR_METHOD_AUTO, NR_METHOD_STAGED, NR_METHOD_FUSED, NR_METHOD_CELLRUN = 0, 1, 2, 3
+NR_METHOD_AUTO, NR_METHOD_STAGED, NR_METHOD_FUSED, NR_METHOD_CELLRUN, NR_METHOD_DIRECT = 0, 1, 2, 3, 4
 
 _PRECISION = {"fp32": NR_FP32, "fp64": NR_FP64, "auto": NR_AUTO}
 _METHOD = {"auto": NR_METHOD_AUTO, "staged": NR_METHOD_STAGED, "fused": NR_METHOD_FUSED,
-           "cellrun": NR_METHOD_CELLRUN}
+           "cellrun": NR_METHOD_CELLRUN, "direct": NR_METHOD_DIRECT}
 
 
 class NrSegment(ctypes.Structure):

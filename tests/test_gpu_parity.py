@@ -64,7 +64,7 @@ def per_instance_errors(X, Xr, off, ok):
 
 # ------------------------------------------------------------ single segment --
 
-@pytest.mark.parametrize("method", ["fused", "staged", "cellrun"])
+@pytest.mark.parametrize("method", ["fused", "staged", "cellrun", "direct"])
 def test_single_segment_fp64(gpu, method):
     say(f"single_segment fp64 {method}")
     w = synth.single_segment()
@@ -78,7 +78,7 @@ def test_single_segment_fp64(gpu, method):
     assert np.allclose(P, np.abs(X) ** 2, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("method", ["fused", "staged", "cellrun"])
+@pytest.mark.parametrize("method", ["fused", "staged", "cellrun", "direct"])
 def test_single_segment_fp32(gpu, method):
     say(f"single_segment fp32 {method}")
     w = synth.single_segment()
@@ -104,7 +104,8 @@ def test_analytic_chirp_collapse_on_gpu(gpu):
 # ------------------------------------------------------------ semicoherent ----
 
 @pytest.mark.parametrize("prec,method", [("fp32", "fused"), ("fp32", "staged"), ("fp32", "cellrun"),
-                                         ("fp64", "fused"), ("fp64", "staged"), ("fp64", "cellrun")])
+                                         ("fp32", "direct"), ("fp64", "fused"), ("fp64", "staged"),
+                                         ("fp64", "cellrun"), ("fp64", "direct")])
 def test_semicoherent_small(gpu, prec, method):
     say(f"semicoherent small {prec} {method}")
     w = synth.semicoherent(hours=0.1, n_mc=4, n_sub=3, seed=3, snr=30.0)
