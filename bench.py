@@ -216,6 +216,7 @@ def stackslide_workload(args, dev):
         _, power, _ = pl.execute(x, want=("power",))
     power_t = ss.nr_ss_transpose(power, len(betas), n_seg, K)
     torch.cuda.synchronize()
+    copy_calibration(args, dev)
     mcs = synth.log_spaced_mc(2048)
     S = 8
     out = {"unit": "tracks/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "f32"}
@@ -264,6 +265,17 @@ def stackslide_workload(args, dev):
                            "sample": f"{len(cand)} seeded tracks of the {n_tracks} (pure-Python FP64 loop)"}
     print(json.dumps(out))
     return out
+
+
+def copy_calibration(args, dev):
+    """One plain device copy of known size, for scaling the memory counters."""
+    import torch
+    if args.copy_mib > 0:
+        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
 
 def _median_ms(fn, reps=5):
@@ -412,13 +424,7 @@ def main():
     log(f"plan: {info.n_inst} instances, {info.n_valid} valid, classes "
         f"{[(c.fp64, c.w, c.n, c.degree, c.parts) for c in cls]}, chunks {info.n_chunks}")
 
-    # copy kernel of known size, for scaling the memory counters
-    if args.copy_mib > 0:
-        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+    copy_calibration(args, dev)
 
     log("timing fp32")
     el, st = time_steps(plan, x32, stat, used, args.steps, args.warmup)
