@@ -87,3 +87,33 @@ def test_ragged_512_sampled(gpu):
         t = w.inst_tol[i]
         bound = max(t, 1e-5) if t >= 1e-6 else max(t, 1e-11)
         assert rel(X[boff[i]:boff[i + 1]], Xr[off[j]:off[j + 1]]) <= bound, (i, t)
+
+
+def test_full_sweep_6h_sampled_sums(gpu):
+    """The 6 h sweep (720 segments x 2048 chirp masses x 20 sub-bands =
+    29,491,200 instances, chunked) in the configuration bench.py times: the
+    segment sums and counts of sampled templates against the oracle."""
+    import torch
+    from paper_2609_12476_amd import Plan
+    say("full sweep 6 h, sampled templates")
+    w = synth.semicoherent(hours=6.0, n_mc=2048, n_sub=20, seed=3, tol=1e-6).as_float32_strain()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with Plan.from_workload(w, precision="fp32", tol=1e-6, use_graph=True, stream=s) as p:
+            assert p.info.n_inst == 29491200
+            x = p.strain_tensor(w.strain, gpu)
+            stat, used = p.semicoherent_sum(x)
+            s.synchronize()
+            S = stat.cpu().numpy().astype(np.float64)
+            U = used.cpu().numpy()
+            soff = p.stat_offsets()
+    rng = np.random.default_rng(29)
+    tm = np.sort(rng.choice(np.flatnonzero(U > 0), size=4, replace=False))
+    sub = synth.Workload(**{**w.__dict__, "mc": w.mc[tm], "f0": w.f0[tm], "f_lo": w.f_lo[tm],
+                            "df": w.df[tm], "n_bins": w.n_bins[tm], "f_max": w.f_max[tm]})
+    Sr, soff_r, used_r = oracle.semicoherent(sub)
+    for q, m in enumerate(tm):
+        assert U[m] == used_r[q]
+        e = rel(S[soff[m]:soff[m + 1]], Sr[soff_r[q]:soff_r[q + 1]])
+        say(f"  template {m}: {U[m]} segments, rel l2 {e:.2e}")
+        assert e <= 1e-4, (m, e)

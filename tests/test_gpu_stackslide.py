@@ -120,3 +120,42 @@ def test_injection_found_end_to_end(gpu):
     for (c, i0_, s) in cand:
         q = i0_ * S + s
         assert abs(ns[c, q] - ref[c, q]) <= NS_TOL * max(1.0, abs(ref[c, q])), (c, i0_, s)
+
+
+def test_fullsize_paper_1h_sampled(gpu):
+    """The benchmark's configuration: the paper's 1 h spectra (120 segments x 69
+    beta x 600 bins) from the NUFFT path, 2048 chirp masses x 120 x 8 start
+    times in the [beta][bin][segment] layout; sampled tracks against the
+    oracle on the same power, and both layouts equal."""
+    import torch
+    from paper_2609_12476_amd import Plan
+    from paper_2609_12476_amd import stackslide as ss
+    say("stack-slide full size")
+    w = synth.paper_bank(hours=1.0).as_float32_strain()
+    n_seg, K, L = w.n_seg, int(w.n_bins[0]), int(w.seg_len[0])
+    with Plan.from_workload(w, precision="fp32", tol=1e-6) as pl:
+        x = pl.strain_tensor(w.strain, gpu)
+        _, pw, _ = pl.execute(x, want=("power",))
+    pt = ss.nr_ss_transpose(pw, len(BETAS), n_seg, K)
+    mcs = synth.log_spaced_mc(2048)
+    S = 8
+    res = []
+    for layout, P in ((1, pt), (0, pw)):
+        with _plan(n_seg, K, mcs, S, L, layout=layout) as p:
+            ns, used = p.execute(P)
+            torch.cuda.synchronize()
+            res.append((ns.cpu().numpy(), used.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    ns, used = res[0]
+    Ph = pw.cpu().numpy().astype(np.float64).reshape(len(BETAS), n_seg, K)
+    rng = np.random.default_rng(13)
+    cand = [(int(c), int(q) // S, int(q) % S) for c, q in
+            zip(rng.integers(0, len(mcs), 200), rng.integers(0, n_seg * S, 200))]
+    ref, cnt = oss.n_sigma(Ph, mcs, S, 30.0, BETAS, 40.0, 1.0 / 30.0, 40.0, 60.0, 2.0 / L, tracks=cand)
+    err = 0.0
+    for (c, i0, s) in cand:
+        q = i0 * S + s
+        assert used[c, q] == cnt[c, q], (c, i0, s)
+        err = max(err, abs(ns[c, q] - ref[c, q]))
+    say(f"  200 sampled tracks: max |d n_sigma| {err:.2e}")
+    assert err <= NS_TOL * max(1.0, float(np.abs(ref[~np.isnan(ref)]).max()))

@@ -59,3 +59,27 @@ def test_fold_and_spectrum_match_oracle(gpu, mc, cplx):
     e = np.linalg.norm(S - Sr) / np.linalg.norm(Sr)
     say(f"  spectrum rel l2 {e:.2e}")
     assert e <= 2e-6
+
+
+def test_comparison_shape_sampled(gpu):
+    """The comparison's 256 s shape at O = 8 over 32 batched segments: every
+    segment's fold equals the first's (same input), and 64 bins around 20 Hz
+    match the oracle's direct sum."""
+    import torch
+    from paper_2609_12476_amd import strobo
+    say("strobo 256 s, O = 8, 32 segments")
+    f0, mc, fs, O, T = 20.0, 1e-2, 512.0, 8, 256.0
+    fs_o = fs * O
+    n = int(T * fs_o)
+    x = (0.5 * np.exp(1j * synth.chirp_phase(np.arange(n) / fs_o, f0, mc, 0.0, 0.3))).astype(np.complex64)
+    xd = torch.from_numpy(x).to(gpu).repeat(32)
+    df = 1.0 / T
+    lo = 20.0 - 32 * df
+    S = strobo.spectrum(xd, fs_o, O, mc, f0, lo, df, 64, n_seg=32)
+    torch.cuda.synchronize()
+    S = S.cpu().numpy().astype(np.complex128)
+    assert np.allclose(S[0], S[-1], rtol=1e-6, atol=1e-6 * np.abs(S[0]).max())
+    ref = ost.spectrum(x.astype(np.complex128), fs_o, O, mc, f0, lo, df, 64)
+    e = np.linalg.norm(S[0] - ref) / np.linalg.norm(ref)
+    say(f"  rel l2 {e:.2e}")
+    assert e <= 2e-6
