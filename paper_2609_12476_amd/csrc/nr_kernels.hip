@@ -134,9 +134,8 @@ __device__ __forceinline__ void horner4(const double* b, double top, double jd0,
     }
 }
 
-__device__ __forceinline__ void dtau4(const TauConsts& t, double top, int j0, double* out)
+__device__ __forceinline__ void dtau4(const TauConsts& t, double top, double jd0, double* out)
 {
-    const double jd0 = (double)j0;
     switch (t.ndeg) {
     case 0:
 #pragma unroll
@@ -152,7 +151,7 @@ __device__ __forceinline__ void dtau4(const TauConsts& t, double top, int j0, do
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const double jd = (double)(j0 + e);
+        const double jd = jd0 + (double)e;
         double acc = t.b[t.ndeg - 1];
         for (int k = t.ndeg - 2; k >= 0; --k) acc = fma(acc, jd, t.b[k]);
         out[e] = acc * jd;
@@ -569,46 +568,74 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
 
 // ------------------------------------------------- cell-run schedule --
 //
-// x_j = df dtau_j - w/(2n) grows with j, so the unwrapped cell index
-// U_j = floor(x_j) n + floor(frac(x_j) n) never decreases and the samples
-// sharing one value of U form a contiguous run.  A wave takes 63 consecutive
-// values of U per round: lane v finds the first sample of run U_0 + 63 r + v
-// by a binary search of uniform length, the next lane's start ends its run,
-// every lane accumulates its run's moments without a cell change, and all
-// lanes flush together.  The strain is read as aligned quads of samples
+// S_j = n (df dtau_j) - w/2 is sample j's grid coordinate in cells, not
+// reduced modulo the grid; it grows with j, so the unwrapped cell index
+// U_j = floor(S_j) never decreases and the samples sharing one value of U
+// form a contiguous run.  A wave takes 63 consecutive values of U per round:
+// lane v finds the first sample of run U_0 + 63 r + v by a bracketed binary
+// search, the next lane's start ends its run, every lane accumulates its
+// run's moments without a cell change (its Chebyshev variable is
+// 1 - 2 (S_j - U), from the same S_j that placed the sample in the run), and
+// all lanes flush together.  The strain is read as aligned quads of samples
 // from a plain per-segment copy.
 
-// U_j and the quantities of sample j that decide it.
-struct CellOf {
-    double x, pos, S, U;
-};
+__device__ __forceinline__ double grid_coord(double dfn, double hnn, double dt) { return fma(dfn, dt, -hnn); }
 
-__device__ __forceinline__ CellOf cell_of(const TauConsts& tc, int j, double nd, double dt)
+// The first sample j in [0, L] with S_j >= t (L if none).  dtau is convex in
+// j (its series has positive coefficients), so S lies below its chord
+// S_0 + m j and above its tangent S_0 + s0 j at j = 0: every j below
+// (t - S_0) / m has S_j < t and every j from (t - S_0) / s0 on has S_j >= t.
+// The search runs inside that bracket, widened by two samples against
+// rounding (inv_m = 1 / m, inv_s0 = 1 / s0).
+__device__ __forceinline__ int first_at_least(const TauConsts& tc, int L, double t, double dfn, double hnn,
+                                              double inv_m, double inv_s0)
 {
-    CellOf c;
-    c.x = fma(tc.df, dt, -tc.hn);
-    c.pos = __builtin_amdgcn_fract(c.x);
-    c.S = c.pos * nd;
-    c.U = fma(floor(c.x), nd, floor(c.S));
-    return c;
-}
-
-// Number of samples j < L with U_j < t.
-__device__ __forceinline__ int first_at_least(const TauConsts& tc, int L, double t, double nd)
-{
-    int pos = 0;
-    for (int step = 1 << (31 - __clz(L)); step > 0; step >>= 1) {
-        const int probe = min(pos + step, L) - 1;
-        const double U = cell_of(tc, probe, nd, dtau_of<false>(tc, probe)).U;
-        if (pos + step <= L && U < t) pos += step;
+    const double d = t + hnn;                     // t - S_0, S_0 = -hnn
+    int lo = (int)fmin(fmax(ceil(d * inv_m) - 2.0, 0.0), (double)L);
+    int hi = (int)fmin(fmax(ceil(d * inv_s0) + 2.0, 0.0), (double)L);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (grid_coord(dfn, hnn, dtau_of<false>(tc, mid)) < t)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-    return pos;
+    return lo;
 }
 
 template <typename E>
 struct alignas(16) Quad {
     E v[4];
 };
+
+// Four consecutive samples q .. q+3 (jq = q as a double) of the cell run
+// whose Chebyshev variable is u = u1 - 2 S_j (u1 = 1 + 2 U) into the
+// moments; MASK: samples outside [js, je) enter with zero strength.
+template <typename T, int D, bool CPLX, bool MASK, typename E>
+__device__ __forceinline__ void cell_quad(const TauConsts& tc, double top, const E* __restrict__ xs, int q,
+                                          double jq, int js, int je, double dfn, double hnn, double u1,
+                                          double fcs, const cpx<T>* tab, Moments<T, D>& M)
+{
+    const Quad<E> xq = *reinterpret_cast<const Quad<E>*>(xs + q);
+    double dt[4];
+    dtau4(tc, top, jq, dt);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int j = q + e;
+        const bool in = MASK ? ((j >= js) & (j < je)) : true;
+        const T u = (T)fma(-2.0, grid_coord(dfn, hnn, dt[e]), u1);
+        T xr, xi, cr, ci;
+        if constexpr (CPLX) {
+            xr = in ? xq.v[e].x : T(0);
+            xi = in ? xq.v[e].y : T(0);
+        } else {
+            xr = in ? xq.v[e] : T(0);
+            xi = T(0);
+        }
+        heterodyne_scaled<T, CPLX>(fcs * dt[e], xr, xi, tab, cr, ci);
+        M.add(u, cr, ci);
+    }
+}
 
 template <typename T, int D, bool CPLX>
 __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t lblock)
@@ -648,54 +675,40 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
         load_tau(tc, d, a.coef, half_width_periods(w, n));
         const double nd = (double)n;
         const int L = d.L;
-        const double U0 = cell_of(tc, 0, nd, dtau_of<false>(tc, 0)).U;
-        const double U1 = cell_of(tc, L - 1, nd, dtau_of<false>(tc, L - 1)).U;
-        const int rounds = uniform(((int)(U1 - U0) + 63) / 63);
-        const E* __restrict__ xs = reinterpret_cast<const E*>(a.strain_lm) + d.strain_off;
-        // per-sample scales: grid position in cells and phase in table steps
+        // per-sample scales: grid coordinate in cells and phase in table steps
         const double dfn = tc.df * nd, hnn = tc.hn * nd;
         const double fcs = tc.fc * (double)(1 << PhaseTable<T>::bits);
+        const double S1 = grid_coord(dfn, hnn, dtau_of<false>(tc, L > 0 ? L - 1 : 0));
+        const double U0 = floor(-hnn), U1 = floor(S1);
+        const int rounds = L > 0 ? uniform(((int)(U1 - U0) + 63) / 63) : 0;
+        // reciprocal slopes of the chord and of the tangent at j = 0
+        const double inv_m = L > 1 ? (double)(L - 1) / (S1 + hnn) : 0.0;
+        const double inv_s0 = 1.0 / (dfn * (tc.ndeg > 0 ? tc.bc[0] : tc.c));
+        const E* __restrict__ xs = reinterpret_cast<const E*>(a.strain_lm) + d.strain_off;
         // leading series coefficient, kept in a vector register
         double top = tc.ndeg > 0 ? tc.b[tc.ndeg - 1] : 0.0;
         asm volatile("" : "+v"(top));
         for (int r = part; r < rounds; r += parts) {
             const double t = U0 + 63.0 * r + (double)lane;
-            const int js = first_at_least(tc, L, t, nd);
+            const int js = first_at_least(tc, L, t, dfn, hnn, inv_m, inv_s0);
             int je = __shfl_down(js, 1);
             if (lane == kWave - 1 || !(t <= U1)) je = js;
+            const double u1 = fma(2.0, t, 1.0);
             Moments<T, D> M;
             M.zero();
-            // whole quads; samples outside the run enter with zero strength
-            // (they lie in the padded copy and have finite positions)
-            for (int q = js & ~3; q < je; q += 4) {
-                const Quad<E> xq = *reinterpret_cast<const Quad<E>*>(xs + q);
-                double dt[4];
-                dtau4(tc, top, q, dt);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int j = q + e;
-                    const bool in = (j >= js) & (j < je);
-                    // position in the cell: frac(x n) = frac(frac(x) n)
-                    const double rr = __builtin_amdgcn_fract(fma(dfn, dt[e], -hnn));
-                    const T u = (T)fma(-2.0, rr, 1.0);
-                    T xr, xi, cr, ci;
-                    if constexpr (CPLX) {
-                        xr = in ? xq.v[e].x : T(0);
-                        xi = in ? xq.v[e].y : T(0);
-                    } else {
-                        xr = in ? xq.v[e] : T(0);
-                        xi = T(0);
-                    }
-                    heterodyne_scaled<T, CPLX>(fcs * dt[e], xr, xi, tab, cr, ci);
-                    M.add(u, cr, ci);
-                }
-            }
+            // whole quads: the first and last quad of a run are masked
+            // (samples outside it enter with zero strength; they lie in the
+            // padded copy and have finite positions), the ones between are not
             if (je > js) {
-                int g = (int)(t - nd * floor(t / nd));
-                if (g >= n) g -= n;
-                if (g < 0) g += n;
-                flush<T, D>(M, g + 1, A, grid, n, w);
+                int q = js & ~3;
+                double jq = (double)q;
+                cell_quad<T, D, CPLX, true>(tc, top, xs, q, jq, js, je, dfn, hnn, u1, fcs, tab, M);
+                for (q += 4, jq += 4.0; q + 4 <= je; q += 4, jq += 4.0)
+                    cell_quad<T, D, CPLX, false>(tc, top, xs, q, jq, js, je, dfn, hnn, u1, fcs, tab, M);
+                if (q < je) cell_quad<T, D, CPLX, true>(tc, top, xs, q, jq, js, je, dfn, hnn, u1, fcs, tab, M);
             }
+            // the support of the points of cell U starts at cell U + 1
+            if (je > js) flush<T, D>(M, (int)t + 1, A, grid, n, w);
         }
     }
     __syncthreads();
