@@ -571,13 +571,13 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
 // S_j = n (df dtau_j) - w/2 is sample j's grid coordinate in cells, not
 // reduced modulo the grid; it grows with j, so the unwrapped cell index
 // U_j = floor(S_j) never decreases and the samples sharing one value of U
-// form a contiguous run.  A wave takes 63 consecutive values of U per round:
-// lane v finds the first sample of run U_0 + 63 r + v by a bracketed binary
-// search, the next lane's start ends its run, every lane accumulates its
-// run's moments without a cell change (its Chebyshev variable is
-// 1 - 2 (S_j - U), from the same S_j that placed the sample in the run), and
-// all lanes flush together.  The strain is read as aligned quads of samples
-// from a plain per-segment copy.
+// form a contiguous run.  A wave takes 64 consecutive cells per round: lane
+// v finds the first sample past the run of cell U_0 + 64 r + v by a
+// bracketed binary search, the lane before it starts there, every
+// lane accumulates its run's moments without a cell change (its Chebyshev
+// variable is 1 - 2 (S_j - U), from the same S_j that placed the sample in
+// the run), and all lanes flush together.  The strain is read as aligned
+// quads of samples from a plain per-segment copy.
 
 __device__ __forceinline__ double grid_coord(double dfn, double hnn, double dt) { return fma(dfn, dt, -hnn); }
 
@@ -680,7 +680,7 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
         const double fcs = tc.fc * (double)(1 << PhaseTable<T>::bits);
         const double S1 = grid_coord(dfn, hnn, dtau_of<false>(tc, L > 0 ? L - 1 : 0));
         const double U0 = floor(-hnn), U1 = floor(S1);
-        const int rounds = L > 0 ? uniform(((int)(U1 - U0) + 63) / 63) : 0;
+        const int rounds = L > 0 ? uniform(((int)(U1 - U0) + kRunsPerRound) / kRunsPerRound) : 0;
         // reciprocal slopes of the chord and of the tangent at j = 0
         const double inv_m = L > 1 ? (double)(L - 1) / (S1 + hnn) : 0.0;
         const double inv_s0 = 1.0 / (dfn * (tc.ndeg > 0 ? tc.bc[0] : tc.c));
@@ -688,12 +688,26 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
         // leading series coefficient, kept in a vector register
         double top = tc.ndeg > 0 ? tc.b[tc.ndeg - 1] : 0.0;
         asm volatile("" : "+v"(top));
+        // end of the previous round's last run (a wave that takes every round
+        // starts each round where the last one ended)
+        int carry = 0;
         for (int r = part; r < rounds; r += parts) {
-            const double t = U0 + 63.0 * r + (double)lane;
-            const int js = first_at_least(tc, L, t, dfn, hnn, inv_m, inv_s0);
-            int je = __shfl_down(js, 1);
-            if (lane == kWave - 1 || !(t <= U1)) je = js;
-            const double u1 = fma(2.0, t, 1.0);
+            // lane v: cell U = U0 + 64 r + v; it searches the end of its run
+            // (the first sample of cell U + 1) and takes the start from the
+            // lane before it
+            const double U = U0 + (double)(kRunsPerRound * r + lane);
+            const int je = first_at_least(tc, L, U + 1.0, dfn, hnn, inv_m, inv_s0);
+            int js = __shfl_up(je, 1);
+            if (lane == 0) {
+                if (r == 0)
+                    js = 0;     // S_0 >= U0 = floor(S_0)
+                else if (parts == 1)
+                    js = carry;
+                else
+                    js = first_at_least(tc, L, U, dfn, hnn, inv_m, inv_s0);
+            }
+            carry = __builtin_amdgcn_readlane(je, kWave - 1);
+            const double u1 = fma(2.0, U, 1.0);
             Moments<T, D> M;
             M.zero();
             // whole quads: the first and last quad of a run are masked
@@ -708,7 +722,7 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
                 if (q < je) cell_quad<T, D, CPLX, true>(tc, top, xs, q, jq, js, je, dfn, hnn, u1, fcs, tab, M);
             }
             // the support of the points of cell U starts at cell U + 1
-            if (je > js) flush<T, D>(M, (int)t + 1, A, grid, n, w);
+            if (je > js) flush<T, D>(M, (int)U + 1, A, grid, n, w);
         }
     }
     __syncthreads();
@@ -728,8 +742,17 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
     }
 }
 
+// Occupancy of the cell-run kernel: six waves per SIMD (at most 80 VGPRs)
+// where the FP32 moments of degree up to 7 fit there without spilling; the
+// rest is left to the compiler.
 template <typename T, int D, bool CPLX>
-__global__ __launch_bounds__(kBlock) void spread_runs_kernel(SpreadArgs a)
+struct RunsWaves {
+    static constexpr int value = (sizeof(T) == 4 && D <= 7) ? 6 : 1;
+};
+
+template <typename T, int D, bool CPLX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RunsWaves<T, D, CPLX>::value))) void
+spread_runs_kernel(SpreadArgs a)
 {
     spread_runs_block<T, D, CPLX>(a, blockIdx.x);
 }

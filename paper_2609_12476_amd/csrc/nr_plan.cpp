@@ -343,10 +343,10 @@ double cells_visited(const InstHost& h, int64_t L, int n, double df)
     return (double)((long double)n * (long double)df * span + 2.0L);
 }
 
-// Rounds of 63 cell runs that one cell-run instance needs.
+// Rounds of cell runs (one per lane) that one cell-run instance needs.
 int cellrun_rounds(const InstHost& h, int64_t L, int n, double df)
 {
-    return (int)std::min(1e6, std::ceil(cells_visited(h, L, n, df) / 63.0));
+    return (int)std::min(1e6, std::ceil(cells_visited(h, L, n, df) / kRunsPerRound));
 }
 
 int default_parts(int64_t L)

@@ -238,6 +238,23 @@ def test_small_and_ragged_sizes(gpu, L, K, mc, prec, method):
     assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
 
 
+@pytest.mark.parametrize("K", [28, 30, 31, 32, 33, 34, 40, 48, 60, 62, 63, 64, 66, 72])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_cellrun_round_edges(gpu, K, prec):
+    """Cell-run instances whose visited cells fall on both sides of one and
+    two full rounds of 64 cells (one run per lane), so that a round's first
+    run starts where the previous round's last one ended."""
+    say(f"cellrun round edges K={K} {prec}")
+    w = synth.random_small(100 + K, 2048, K, 3e-2, f0=50.0, fs=64.0, t_start=300.0)
+    Xr, off, ok = oracle.spectra(w)
+    X, _, valid, _, cls = run_plan(w, gpu, precision=prec, method="cellrun",
+                                   tol=1e-6 if prec == "fp32" else 1e-10)
+    span = oracle.dtau(3e-2, 50.0, 300.0, 64.0, 2048)[-1]
+    say(f"  grid {cls[0].n}, about {cls[0].n * span / 32.0 + 1:.1f} cells visited")
+    assert valid[0] == ok[0] == 1
+    assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
+
+
 @pytest.mark.parametrize("method", ["fused", "staged", "cellrun"])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_complex_strain(gpu, prec, method):
