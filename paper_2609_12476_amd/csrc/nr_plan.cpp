@@ -604,6 +604,17 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
                                          " (lower n_bins or sigma)");
         // tau series of the instance (ndeg < 0: the log1p/expm1 form)
         const double df_i = t.df > 0.0 ? t.df : g.fs / (double)g.n_samples;
+        {
+            // the heterodyne phase, counted in phase-table steps (at most
+            // 1024 per cycle), must stay below 2^48: beyond that FP64 no
+            // longer resolves a sixteenth of a step
+            const long double span = h.beta == 0.0 ? h.c * (long double)(g.n_samples - 1)
+                                                    : h.a * (1.0L - powl(1.0L - (long double)h.y_max, 0.625L));
+            const double fc = t.f_lo + (double)(K / 2) * df_i;
+            if (std::fabs(fc) * (double)span * 1024.0 >= 281474976710656.0)
+                fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) +
+                                             ": heterodyne frequency x duration too large (over 2^38 cycles)");
+        }
         series.clear();
         int ndeg = 0;
         if (h.beta != 0.0) {
