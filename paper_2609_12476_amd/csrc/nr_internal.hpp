@@ -124,13 +124,26 @@ struct EpilogueOut {
 // max_entries: the largest parts * C * 64 of the segments (sizes the grid).
 hipError_t launch_strain_lane_major(const SegDev* segs, int32_t n_segs, int64_t max_entries, const void* strain,
                                     int strain_fp64, int strain_complex, int dst_fp64, hipStream_t st);
-// One launch over several classes of the same kernel instantiation: tab
-// holds their arguments (device), block_off[ncls + 1] their first workgroup.
-hipError_t launch_spread_multi(const SpreadArgs* tab, const int64_t* block_off, int ncls,
-                               int64_t blocks, int fp64, int deg, int fused, int cplx, int snap,
-                               size_t lds, hipStream_t st);
-hipError_t launch_epilogue_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls,
-                                 int64_t blocks, int sum_mode, EpilogueOut out, int fp64,
+// One launch over up to kGroupMax classes of the same kernel instantiation:
+// their arguments travel in the kernel arguments (so that the kernel knows
+// every pointer in them addresses global memory), block_off[c] is the first
+// workgroup of class c.
+constexpr int kGroupMax = 8;
+struct SpreadTable {
+    SpreadArgs a[kGroupMax];
+    int64_t block_off[kGroupMax];
+    int32_t ncls;
+};
+hipError_t launch_spread_multi(const SpreadTable& t, int64_t blocks, int fp64, int deg, int fused, int cplx,
+                               int snap, size_t lds, hipStream_t st);
+// The same for the epilogue: block_off[m][c] is the first workgroup of class
+// c in mode m (0 spectra or power rows, 1 segment sum or row sums).
+struct EpilogueTable {
+    EpilogueArgs a[kGroupMax];
+    int64_t block_off[2][kGroupMax];
+    int32_t ncls;
+};
+hipError_t launch_epilogue_multi(const EpilogueTable& t, int64_t blocks, int sum_mode, EpilogueOut out, int fp64,
                                  int out_fp64, size_t lds, hipStream_t st);
 int64_t epilogue_blocks(const EpilogueArgs& a, int sum_mode);
 hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st);
@@ -145,8 +158,8 @@ hipError_t launch_epilogue_spectra(const EpilogueArgs& a, const EpilogueOut& out
 // Second pass of the two-pass segment sum: stat += weighted sums of the
 // power rows of each class template (one workgroup per template).
 hipError_t launch_rows_sum(const EpilogueArgs& a, const EpilogueOut& out, int out_fp64, hipStream_t st);
-hipError_t launch_rows_sum_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
-                                 EpilogueOut out, int out_fp64, hipStream_t st);
+hipError_t launch_rows_sum_multi(const EpilogueTable& t, int64_t blocks, EpilogueOut out, int out_fp64,
+                                 hipStream_t st);
 hipError_t launch_epilogue_sum(const EpilogueArgs& a, const EpilogueOut& out, int fp64, int out_fp64,
                                hipStream_t st);
 hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,

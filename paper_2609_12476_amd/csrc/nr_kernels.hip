@@ -48,6 +48,7 @@ struct PointOf<double> {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+
 // ------------------------------------------------------------------ tau --
 
 constexpr int kHornerFast = 16;   // tau series degrees evaluated from registers
@@ -766,23 +767,18 @@ __device__ __forceinline__ int class_of_block(const int64_t* __restrict__ block_
 }
 
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-__global__ __launch_bounds__(kBlock) void spread_multi_kernel(const SpreadArgs* __restrict__ tab,
-                                                              const int64_t* __restrict__ block_off,
-                                                              int ncls)
+__global__ __launch_bounds__(kBlock) void spread_multi_kernel(const SpreadTable t)
 {
-    const int c = class_of_block(block_off, ncls, blockIdx.x);
-    const SpreadArgs a = tab[c];
-    spread_block<T, D, FUSED, CPLX, SNAP>(a, (int64_t)blockIdx.x - block_off[c]);
+    const int c = class_of_block(t.block_off, t.ncls, blockIdx.x);
+    spread_block<T, D, FUSED, CPLX, SNAP>(t.a[c], (int64_t)blockIdx.x - t.block_off[c]);
 }
 
 template <typename T, int D, bool CPLX>
-__global__ __launch_bounds__(kBlock) void spread_runs_multi_kernel(const SpreadArgs* __restrict__ tab,
-                                                                   const int64_t* __restrict__ block_off,
-                                                                   int ncls)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RunsWaves<T, D, CPLX>::value))) void
+spread_runs_multi_kernel(const SpreadTable t)
 {
-    const int c = class_of_block(block_off, ncls, blockIdx.x);
-    const SpreadArgs a = tab[c];
-    spread_runs_block<T, D, CPLX>(a, (int64_t)blockIdx.x - block_off[c]);
+    const int c = class_of_block(t.block_off, t.ncls, blockIdx.x);
+    spread_runs_block<T, D, CPLX>(t.a[c], (int64_t)blockIdx.x - t.block_off[c]);
 }
 
 // ------------------------------------------------------------------ FFT --
@@ -1029,13 +1025,10 @@ __global__ __launch_bounds__(kBlock) void rows_sum_kernel(EpilogueArgs a, Epilog
 }
 
 template <typename O>
-__global__ __launch_bounds__(kBlock) void rows_sum_multi_kernel(const EpilogueArgs* __restrict__ tab,
-                                                                const int64_t* __restrict__ block_off, int ncls,
-                                                                EpilogueOut o)
+__global__ __launch_bounds__(kBlock) void rows_sum_multi_kernel(const EpilogueTable t, EpilogueOut o)
 {
-    const int c = class_of_block(block_off, ncls, blockIdx.x);
-    const EpilogueArgs& a = tab[c];  // read in place: a private copy would spill the radix list
-    rows_sum_block<O>(a, o, (int64_t)blockIdx.x - block_off[c]);
+    const int c = class_of_block(t.block_off[1], t.ncls, blockIdx.x);
+    rows_sum_block<O>(t.a[c], o, (int64_t)blockIdx.x - t.block_off[1][c]);
 }
 
 // Segment sum: one workgroup per template; its instances inside the chunk
@@ -1122,13 +1115,11 @@ __global__ __launch_bounds__(kBlock) void epilogue_kernel(EpilogueArgs a, Epilog
 }
 
 template <typename T, typename O, int SUM>
-__global__ __launch_bounds__(kBlock) void epilogue_multi_kernel(const EpilogueArgs* __restrict__ tab,
-                                                                const int64_t* __restrict__ block_off,
-                                                                int ncls, EpilogueOut o)
+__global__ __launch_bounds__(kBlock) void epilogue_multi_kernel(const EpilogueTable t, EpilogueOut o)
 {
-    const int c = class_of_block(block_off, ncls, blockIdx.x);
-    const EpilogueArgs& a = tab[c];  // read in place: a private copy would spill the radix list
-    const int64_t lb = (int64_t)blockIdx.x - block_off[c];
+    const int c = class_of_block(t.block_off[SUM], t.ncls, blockIdx.x);
+    const EpilogueArgs& a = t.a[c];  // read in place: a private copy would spill the radix list
+    const int64_t lb = (int64_t)blockIdx.x - t.block_off[SUM][c];
     if (SUM)
         epilogue_sum_block<T, O>(a, o, lb);
     else
@@ -1398,18 +1389,11 @@ static void launch_spread_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStrea
     spread_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(a);
 }
 
-// Arguments of a multi-class launch (the same kernel instantiation).
-struct MultiSpread {
-    const SpreadArgs* tab;
-    const int64_t* block_off;
-    int ncls;
-};
-
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-static void launch_spread_k(const MultiSpread& m, dim3 grid, size_t lds, hipStream_t st)
+static void launch_spread_k(const SpreadTable& m, dim3 grid, size_t lds, hipStream_t st)
 {
     allow_lds(spread_multi_kernel<T, D, FUSED, CPLX, SNAP>, lds);
-    spread_multi_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(m.tab, m.block_off, m.ncls);
+    spread_multi_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(m);
 }
 
 template <typename T, int D, bool CPLX>
@@ -1420,10 +1404,10 @@ static void launch_runs_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStream_
 }
 
 template <typename T, int D, bool CPLX>
-static void launch_runs_k(const MultiSpread& m, dim3 grid, size_t lds, hipStream_t st)
+static void launch_runs_k(const SpreadTable& m, dim3 grid, size_t lds, hipStream_t st)
 {
     allow_lds(spread_runs_multi_kernel<T, D, CPLX>, lds);
-    spread_runs_multi_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(m.tab, m.block_off, m.ncls);
+    spread_runs_multi_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(m);
 }
 
 template <typename T, int D, bool SNAP, typename A>
@@ -1482,13 +1466,13 @@ hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipS
                 : launch_spread_t<float>(a, deg, fused, a.strain_complex, a.snap, blocks, lds, st);
 }
 
-hipError_t launch_spread_multi(const SpreadArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
-                               int fp64, int deg, int fused, int cplx, int snap, size_t lds, hipStream_t st)
+hipError_t launch_spread_multi(const SpreadTable& t, int64_t blocks, int fp64, int deg, int fused, int cplx,
+                               int snap, size_t lds, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
-    const MultiSpread m{tab, block_off, ncls};
-    return fp64 ? launch_spread_t<double>(m, deg, fused, cplx, snap, blocks, lds, st)
-                : launch_spread_t<float>(m, deg, fused, cplx, snap, blocks, lds, st);
+    if (t.ncls < 1 || t.ncls > kGroupMax) return hipErrorInvalidValue;
+    return fp64 ? launch_spread_t<double>(t, deg, fused, cplx, snap, blocks, lds, st)
+                : launch_spread_t<float>(t, deg, fused, cplx, snap, blocks, lds, st);
 }
 
 int64_t epilogue_blocks(const EpilogueArgs& a, int sum_mode)
@@ -1508,11 +1492,11 @@ static hipError_t launch_epi_k(const EpilogueArgs& a, const EpilogueOut& o, int6
 }
 
 template <typename T, typename O, int SUM>
-static hipError_t launch_epi_multi_k(const EpilogueArgs* tab, const int64_t* off, int ncls, const EpilogueOut& o,
-                                     int64_t blocks, size_t lds, hipStream_t st)
+static hipError_t launch_epi_multi_k(const EpilogueTable& t, const EpilogueOut& o, int64_t blocks, size_t lds,
+                                     hipStream_t st)
 {
     allow_lds(epilogue_multi_kernel<T, O, SUM>, lds);
-    epilogue_multi_kernel<T, O, SUM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(tab, off, ncls, o);
+    epilogue_multi_kernel<T, O, SUM><<<dim3((unsigned)blocks), dim3(kBlock), lds, st>>>(t, o);
     return hipGetLastError();
 }
 
@@ -1549,30 +1533,32 @@ hipError_t launch_rows_sum(const EpilogueArgs& a, const EpilogueOut& o, int out_
     return hipGetLastError();
 }
 
-hipError_t launch_rows_sum_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
-                                 EpilogueOut o, int out_fp64, hipStream_t st)
+hipError_t launch_rows_sum_multi(const EpilogueTable& t, int64_t blocks, EpilogueOut o, int out_fp64,
+                                 hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
+    if (t.ncls < 1 || t.ncls > kGroupMax) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks), block(kBlock);
     if (out_fp64)
-        rows_sum_multi_kernel<double><<<grid, block, 0, st>>>(tab, block_off, ncls, o);
+        rows_sum_multi_kernel<double><<<grid, block, 0, st>>>(t, o);
     else
-        rows_sum_multi_kernel<float><<<grid, block, 0, st>>>(tab, block_off, ncls, o);
+        rows_sum_multi_kernel<float><<<grid, block, 0, st>>>(t, o);
     return hipGetLastError();
 }
 
-hipError_t launch_epilogue_multi(const EpilogueArgs* tab, const int64_t* block_off, int ncls, int64_t blocks,
-                                 int sum_mode, EpilogueOut o, int fp64, int out_fp64, size_t lds, hipStream_t st)
+hipError_t launch_epilogue_multi(const EpilogueTable& t, int64_t blocks, int sum_mode, EpilogueOut o, int fp64,
+                                 int out_fp64, size_t lds, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
+    if (t.ncls < 1 || t.ncls > kGroupMax) return hipErrorInvalidValue;
     if (sum_mode) {
-        if (fp64) return launch_epi_multi_k<double, double, 1>(tab, block_off, ncls, o, blocks, lds, st);
-        if (out_fp64) return launch_epi_multi_k<float, double, 1>(tab, block_off, ncls, o, blocks, lds, st);
-        return launch_epi_multi_k<float, float, 1>(tab, block_off, ncls, o, blocks, lds, st);
+        if (fp64) return launch_epi_multi_k<double, double, 1>(t, o, blocks, lds, st);
+        if (out_fp64) return launch_epi_multi_k<float, double, 1>(t, o, blocks, lds, st);
+        return launch_epi_multi_k<float, float, 1>(t, o, blocks, lds, st);
     }
-    if (fp64) return launch_epi_multi_k<double, double, 0>(tab, block_off, ncls, o, blocks, lds, st);
-    if (out_fp64) return launch_epi_multi_k<float, double, 0>(tab, block_off, ncls, o, blocks, lds, st);
-    return launch_epi_multi_k<float, float, 0>(tab, block_off, ncls, o, blocks, lds, st);
+    if (fp64) return launch_epi_multi_k<double, double, 0>(t, o, blocks, lds, st);
+    if (out_fp64) return launch_epi_multi_k<float, double, 0>(t, o, blocks, lds, st);
+    return launch_epi_multi_k<float, float, 0>(t, o, blocks, lds, st);
 }
 
 hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,

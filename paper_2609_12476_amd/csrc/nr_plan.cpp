@@ -114,7 +114,8 @@ struct Group {
     int fp64 = 0, deg = 0, fused = 1, snap = 0;
     size_t lds[2] = {0, 0};            // spread: [0]; epilogue: [0] spectra, [1] segment sum
     int64_t blocks[2] = {0, 0};
-    DevBuf d_tab, d_off[2];
+    SpreadTable spread{};              // class tables (kernel arguments)
+    EpilogueTable epi{};
 };
 
 }  // namespace
@@ -991,6 +992,10 @@ void build_groups(nr_plan_s& P)
         const size_t sl = spread_lds_bytes(c.fp64, c.n);
         const std::array<int, 5> sk{c.fp64, c.deg, fused, snap, lds_tier(sl)};
         auto it = sg.find(sk);
+        if (it != sg.end() && P.spread_groups[it->second].cls.size() >= (size_t)kGroupMax) {
+            sg.erase(it);    // full: later classes of this kind start a new group
+            it = sg.end();
+        }
         if (it == sg.end()) {
             it = sg.emplace(sk, P.spread_groups.size()).first;
             P.spread_groups.emplace_back();
@@ -1008,6 +1013,7 @@ void build_groups(nr_plan_s& P)
         std::vector<size_t>& cand = eg[ek];
         size_t gi = SIZE_MAX;
         for (size_t q : cand) {
+            if (P.epi_groups[q].cls.size() >= (size_t)kGroupMax) continue;
             bool clash = false;
             for (int32_t t : c.tmpl_id) clash = clash || eg_tmpls[q][t];
             if (!clash) {
@@ -1029,33 +1035,28 @@ void build_groups(nr_plan_s& P)
         e.lds[1] = std::max(e.lds[1], el);
     }
     for (Group& g : P.spread_groups) {
-        std::vector<SpreadArgs> tab;
-        std::vector<int64_t> off{0};
-        for (int ci : g.cls) {
-            const Class& c = *P.classes[ci];
-            tab.push_back(spread_args(P, c, c.chunks[0]));
-            off.push_back(off.back() + spread_blocks(c.chunks[0].count, c.parts));
+        int64_t off = 0;
+        g.spread.ncls = (int32_t)g.cls.size();
+        for (size_t q = 0; q < g.cls.size(); ++q) {
+            const Class& c = *P.classes[g.cls[q]];
+            g.spread.a[q] = spread_args(P, c, c.chunks[0]);
+            g.spread.block_off[q] = off;
+            off += spread_blocks(c.chunks[0].count, c.parts);
         }
-        g.blocks[0] = off.back();
-        g.d_tab.upload(tab, "class table");
-        g.d_off[0].upload(off, "class table");
+        g.blocks[0] = off;
     }
     for (Group& g : P.epi_groups) {
-        std::vector<EpilogueArgs> tab;
-        std::vector<int64_t> off[2];
-        off[0].push_back(0);
-        off[1].push_back(0);
-        for (int ci : g.cls) {
-            const Class& c = *P.classes[ci];
-            const EpilogueArgs e = epilogue_args(P, c, c.chunks[0]);
-            tab.push_back(e);
-            for (int m = 0; m < 2; ++m) off[m].push_back(off[m].back() + epilogue_blocks(e, m));
+        int64_t off[2] = {0, 0};
+        g.epi.ncls = (int32_t)g.cls.size();
+        for (size_t q = 0; q < g.cls.size(); ++q) {
+            const Class& c = *P.classes[g.cls[q]];
+            g.epi.a[q] = epilogue_args(P, c, c.chunks[0]);
+            for (int m = 0; m < 2; ++m) {
+                g.epi.block_off[m][q] = off[m];
+                off[m] += epilogue_blocks(g.epi.a[q], m);
+            }
         }
-        g.d_tab.upload(tab, "class table");
-        for (int m = 0; m < 2; ++m) {
-            g.blocks[m] = off[m].back();
-            g.d_off[m].upload(off[m], "class table");
-        }
+        for (int m = 0; m < 2; ++m) g.blocks[m] = off[m];
     }
 }
 
@@ -1148,9 +1149,8 @@ void run_front_batched(nr_plan_s& P)
             continue;
         }
         timed_launch(P, NR_STAGE_SPREAD, [&] {
-            return launch_spread_multi((const SpreadArgs*)g.d_tab.p, (const int64_t*)g.d_off[0].p, (int)g.cls.size(),
-                                       g.blocks[0], g.fp64, g.deg, g.fused, P.opt.strain_complex, g.snap, g.lds[0],
-                                       st);
+            return launch_spread_multi(g.spread, g.blocks[0], g.fp64, g.deg, g.fused, P.opt.strain_complex, g.snap,
+                                       g.lds[0], st);
         }, "spread kernel");
     }
     join_side(P, 0, ns);
@@ -1176,9 +1176,7 @@ void run_epilogue_batched(nr_plan_s& P, int mode, const EpilogueOut& out)
             continue;
         }
         timed_launch(P, NR_STAGE_EPILOGUE, [&] {
-            return launch_epilogue_multi((const EpilogueArgs*)g.d_tab.p, (const int64_t*)g.d_off[mode].p,
-                                         (int)g.cls.size(), g.blocks[mode], mode, out, g.fp64, P.out_fp64,
-                                         g.lds[mode], st);
+            return launch_epilogue_multi(g.epi, g.blocks[mode], mode, out, g.fp64, P.out_fp64, g.lds[mode], st);
         }, mode ? "segment sum" : "epilogue");
     }
     join_side(P, 1, ns);
@@ -1309,8 +1307,7 @@ void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, vo
                     continue;
                 }
                 timed_launch(P, NR_STAGE_EPILOGUE, [&] {
-                    return launch_rows_sum_multi((const EpilogueArgs*)g.d_tab.p, (const int64_t*)g.d_off[1].p,
-                                                 (int)g.cls.size(), g.blocks[1], out, P.out_fp64, P.stream);
+                    return launch_rows_sum_multi(g.epi, g.blocks[1], out, P.out_fp64, P.stream);
                 }, "segment sum");
             }
             return;

@@ -247,7 +247,7 @@ def test_cellrun_round_edges(gpu, K, prec):
     say(f"cellrun round edges K={K} {prec}")
     w = synth.random_small(100 + K, 2048, K, 3e-2, f0=50.0, fs=64.0, t_start=300.0)
     Xr, off, ok = oracle.spectra(w)
-    X, _, valid, _, cls = run_plan(w, gpu, precision=prec, method="cellrun",
+    X, _, valid, _, cls = run_plan(w, gpu, precision=prec, method="cellrun", sigma=2.0,
                                    tol=1e-6 if prec == "fp32" else 1e-10)
     span = oracle.dtau(3e-2, 50.0, 300.0, 64.0, 2048)[-1]
     say(f"  grid {cls[0].n}, about {cls[0].n * span / 32.0 + 1:.1f} cells visited")
