@@ -148,6 +148,7 @@ def other_workload(args, dev):
             w = synth.semicoherent(hours=6.0, n_mc=2048, n_sub=20, seed=3, tol=1e-6).as_float32_strain()
             kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune, method=args.method)
             mode = "sum"
+        kw.update(flush_period=args.flush_period, moment_mode=args.moment_mode)
         log(f"{w.name}: planning {w.n_inst} instances")
         t0 = time.perf_counter()
         plan = Plan.from_workload(w, stream=stream, **kw)

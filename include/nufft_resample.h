@@ -79,7 +79,8 @@ typedef enum {
 
 typedef enum {
     NR_METHOD_AUTO = 0,   /* per instance: NR_METHOD_CELLRUN when its time series spends
-                             at least 24 samples in each grid cell it visits or its
+                             at least 24 samples (12 in plans of 4096 or more
+                             instances) in each grid cell it visits or its
                              spreader workgroup needs at most 1/5 of a compute unit's
                              LDS; else NR_METHOD_FUSED */
     NR_METHOD_STAGED = 1, /* tau kernel writes a point stream; spreader reads it */

@@ -358,13 +358,16 @@ int default_parts(int64_t L)
 }
 
 // Waves per cell-run instance (its rounds are dealt to its waves in turn).
-// Plans too small to fill the GPU: as many as there are rounds, up to 16;
-// otherwise the sample-run rule, keeping at least four rounds per wave.
-int cellrun_parts(int rounds, bool small_plan, int64_t L)
+// Plans too small to fill the GPU (plan_waves at one wave per instance):
+// more waves, up to 16 and one round each, while the plan has fewer than
+// 8192 waves, then only while every wave keeps four rounds (a wave's fixed
+// cost, zeroing and reducing its grid copy, is then amortised); otherwise
+// the sample-run rule, keeping at least four rounds per wave.
+int cellrun_parts(int rounds, bool small_plan, int64_t L, int64_t plan_waves)
 {
     int p = 1;
     if (small_plan) {
-        while (p * 2 <= 16 && p * 2 <= rounds) p *= 2;
+        while (p * 2 <= 16 && p * 2 <= rounds && (plan_waves * p < 8192 || rounds >= 4 * p * 2)) p *= 2;
     } else {
         while (p * 2 <= default_parts(L) && rounds >= 4 * p * 2) p *= 2;
     }
@@ -374,9 +377,16 @@ int cellrun_parts(int rounds, bool small_plan, int64_t L)
 // Automatic spreader: cell runs, unless the time series spends fewer than
 // kCellRunMinDensity samples in each cell it visits AND the spreader's LDS
 // leaves fewer than five workgroups per compute unit (sparse runs pay more
-// for the boundary search and partly used quads than they save, and that
-// search's dependent chain needs resident waves to hide behind).
+// for the run search and partly used quads than they save, and that
+// search's dependent chain needs resident waves to hide behind).  The
+// density bar is lower in plans with at least 4096 instances: measured on
+// the beta bank (8280 instances, 12.8 samples per cell, n = 1200) cell runs
+// with four waves per instance take 1.01 ms per step against 1.11 ms for
+// sample runs, while on the 512-instance ragged batch the same switch for its
+// 12.8-sample classes costs 0.318 -> 0.350 ms.
 constexpr double kCellRunMinDensity = 24.0;
+constexpr double kCellRunMinDensityLarge = 12.0;
+constexpr int64_t kLargePlanWaves = 4096;
 constexpr size_t kCellRunMaxSparseLds = kLdsBytes / 5;
 
 // Waves per instance when the whole plan has too few waves to fill the chip:
@@ -563,10 +573,12 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     }
     // plans with few waves: spread each instance over more waves
     bool small_plan = false;
+    int64_t plan_waves = 0;
     if (o.parts == 0) {
         int64_t waves = 0;
         for (int64_t i = 0; i < N && waves < 16384; ++i) waves += default_parts(P.segs[P.inst_seg[i]].n_samples);
         small_plan = waves < 16384;
+        plan_waves = waves;
     }
     std::vector<double> tmpl_beta(n_tmpls);
     for (int32_t m = 0; m < n_tmpls; ++m) tmpl_beta[m] = chirp_beta(P.tmpls[m].mc_msun, P.tmpls[m].f0);
@@ -624,12 +636,14 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         }
         int method = resolve_method(o.method);
         if (o.method == NR_METHOD_AUTO &&
-            ((double)g.n_samples >= kCellRunMinDensity * cells_visited(h, g.n_samples, n, df_i) ||
+            ((double)g.n_samples >= (small_plan && plan_waves < kLargePlanWaves ? kCellRunMinDensity
+                                                                                : kCellRunMinDensityLarge) *
+                                        cells_visited(h, g.n_samples, n, df_i) ||
              spread_lds_bytes(fp64, n) <= kCellRunMaxSparseLds))
             method = NR_METHOD_CELLRUN;
         int parts = o.parts ? o.parts : small_plan ? small_plan_parts(g.n_samples) : default_parts(g.n_samples);
         if (method == NR_METHOD_CELLRUN && o.parts == 0)
-            parts = cellrun_parts(cellrun_rounds(h, g.n_samples, n, df_i), small_plan, g.n_samples);
+            parts = cellrun_parts(cellrun_rounds(h, g.n_samples, n, df_i), small_plan, g.n_samples, plan_waves);
         int flush = o.flush_period;
         int snap = o.moment_mode == 2 ? 1 : 0;
         if (o.tune) {
