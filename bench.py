@@ -395,8 +395,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(sharding by template is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path (instances are "
+              "independent; several GPUs would each take a share of the templates).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -14,7 +14,7 @@ selection bookkeeping):
                 injections the pipeline generates, against noise-only draws.
   refinement    the top-k regions' fine templates (8 per coarse cell,
                 log-spaced inside the cell) are searched; the exhaustive fine
-                grid is the fallback and the judge.
+                grid is the fallback and the reference it is scored against.
 
 Region and label convention: a region is (coarse cell m, sub-band b); an
 injection (Mc, f) belongs to the region whose cell contains
