@@ -107,8 +107,13 @@ struct Class {
         d_tmpl_list_off, d_tmpl_stat_off, d_entry_seg;
 };
 
+// The class tables of grouped launches travel in the kernel arguments
+// (limited to 4 KiB).
+static_assert(sizeof(SpreadTable) <= 2048 && sizeof(EpilogueTable) + sizeof(EpilogueOut) <= 2048,
+              "class tables must fit the kernel argument segment");
+
 // Classes launched together: one kernel instantiation and one LDS
-// occupancy tier, each class's arguments in a device table.
+// occupancy tier, each class's arguments in a table of the kernel arguments.
 struct Group {
     std::vector<int> cls;
     int fp64 = 0, deg = 0, fused = 1, snap = 0;
