@@ -59,27 +59,35 @@ __global__ void refresh_bf16_kernel(const float* __restrict__ p, bf16_t* __restr
 
 // ------------------------------------------------------------- forward --
 
-// acc[r] += sum_k src[r][k] * wt[k][j] for the workgroup's RB rows; src in
-// LDS (row-major, width kw), wt bfloat16 [kw][HID] in global memory.
-template <int KW>
-__device__ __forceinline__ void rows_times_column(const float* __restrict__ src,
-                                                  const bf16_t* __restrict__ wt, int j,
-                                                  float (&acc)[RB])
+// The two hidden layers are dense products [RB rows x KW] x [KW x HID] on
+// the matrix cores: v_mfma_f32_32x32x2f32 takes FP32 activations and the
+// bfloat16 weights widened exactly to FP32, so the products keep the FP32
+// activation precision.  Wave wv of the workgroup owns output columns
+// 64 wv .. 64 wv + 63 as two 32 x 32 tiles.  Operand layout of the
+// instruction (lane l, m = l % 32, h = l / 32): A[m][k = h], B[k = h][n = m];
+// accumulator e of lane l is C[8 (e / 4) + 4 h + e % 4][m].
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int XS = IN + 1, HS = HID + 1;   // LDS row strides (odd: no bank conflicts)
+
+__device__ __forceinline__ int tile_row(int e, int h) { return 8 * (e >> 2) + 4 * h + (e & 3); }
+
+template <int KW, int STRIDE>
+__device__ __forceinline__ void rows_times_weights(const float* __restrict__ src, const bf16_t* __restrict__ wt,
+                                                   int n0, floatx16& c0, floatx16& c1)
 {
-    for (int k = 0; k < KW; k += 4) {
-        const float w0 = from_bf16(wt[(k + 0) * HID + j]);
-        const float w1 = from_bf16(wt[(k + 1) * HID + j]);
-        const float w2 = from_bf16(wt[(k + 2) * HID + j]);
-        const float w3 = from_bf16(wt[(k + 3) * HID + j]);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const float4 x = *reinterpret_cast<const float4*>(src + r * KW + k);
-            acc[r] = fmaf(x.x, w0, fmaf(x.y, w1, fmaf(x.z, w2, fmaf(x.w, w3, acc[r]))));
-        }
+    const int l = threadIdx.x & 63;
+    const int m = l & 31, h = l >> 5;
+    for (int k = 0; k < KW; k += 2) {
+        const float a = src[m * STRIDE + k + h];
+        const float b0 = from_bf16(wt[(k + h) * HID + n0 + m]);
+        const float b1 = from_bf16(wt[(k + h) * HID + n0 + 32 + m]);
+        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, c1, 0, 0, 0);
     }
 }
 
-// One workgroup per RB rows, one thread per hidden unit j.
+// One workgroup per RB = 32 rows (four waves).
 __global__ __launch_bounds__(BLK) void forward_kernel(const float* __restrict__ x, int64_t B,
                                                       const float* __restrict__ p,
                                                       const bf16_t* __restrict__ w1t,
@@ -89,46 +97,68 @@ __global__ __launch_bounds__(BLK) void forward_kernel(const float* __restrict__ 
                                                       float* __restrict__ h2_out,
                                                       float* __restrict__ z_out)
 {
-    __shared__ __align__(16) float xs[RB * IN];
-    __shared__ __align__(16) float hs[RB * HID];
+    static_assert(RB == 32 && BLK == 256 && HID == 256, "four waves of two 32 x 32 tiles");
+    __shared__ float xs[RB * XS];
+    __shared__ float hs[RB * HS];
     __shared__ float red[4][RB];
-    const int j = threadIdx.x;
+    const int t = threadIdx.x;
+    const int l = t & 63, wv = t >> 6;
+    const int m = l & 31, h = l >> 5;
+    const int n0 = 64 * wv;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
     const int nr = (int)((B - r0) < RB ? (B - r0) : RB);
-    for (int i = j; i < RB * IN; i += BLK) {
-        const int r = i / IN;
-        xs[i] = r < nr ? x[(r0 + r) * IN + (i % IN)] : 0.0f;
+    for (int i = t; i < RB * IN; i += BLK) {
+        const int r = i / IN, k = i % IN;
+        xs[r * XS + k] = r < nr ? x[(r0 + r) * IN + k] : 0.0f;
     }
     __syncthreads();
-    float acc[RB];
-    const float b1 = p[OFF_B1 + j];
+    floatx16 c0, c1;
+    {
+        const float b0 = p[OFF_B1 + n0 + m], b1 = p[OFF_B1 + n0 + 32 + m];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = b1;
-    rows_times_column<IN>(xs, w1t, j, acc);
+        for (int e = 0; e < 16; ++e) {
+            c0[e] = b0;
+            c1[e] = b1;
+        }
+    }
+    rows_times_weights<IN, XS>(xs, w1t, n0, c0, c1);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        const float h = fmaxf(acc[r], 0.0f);
-        hs[r * HID + j] = h;
-        if (h1_out && r < nr) h1_out[(r0 + r) * HID + j] = h;
+    for (int e = 0; e < 16; ++e) {
+        const int r = tile_row(e, h);
+        const float v0 = fmaxf(c0[e], 0.0f), v1 = fmaxf(c1[e], 0.0f);
+        hs[r * HS + n0 + m] = v0;
+        hs[r * HS + n0 + 32 + m] = v1;
+        if (h1_out && r < nr) {
+            h1_out[(r0 + r) * HID + n0 + m] = v0;
+            h1_out[(r0 + r) * HID + n0 + 32 + m] = v1;
+        }
     }
     __syncthreads();
-    const float b2 = p[OFF_B2 + j];
+    {
+        const float b0 = p[OFF_B2 + n0 + m], b1 = p[OFF_B2 + n0 + 32 + m];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = b2;
-    rows_times_column<HID>(hs, w2t, j, acc);
-    const float wj = from_bf16(w3[j]);
-    const int lane = j & 63, wave = j >> 6;
+        for (int e = 0; e < 16; ++e) {
+            c0[e] = b0;
+            c1[e] = b1;
+        }
+    }
+    rows_times_weights<HID, HS>(hs, w2t, n0, c0, c1);
+    const float w0 = from_bf16(w3[n0 + m]), w1 = from_bf16(w3[n0 + 32 + m]);
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-        const float h = fmaxf(acc[r], 0.0f);
-        if (h2_out && r < nr) h2_out[(r0 + r) * HID + j] = h;
-        // sum over the 64 units of the wave, in a fixed butterfly order
-        float v = h * wj;
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) red[wave][r] = v;
+    for (int e = 0; e < 16; ++e) {
+        const int r = tile_row(e, h);
+        const float v0 = fmaxf(c0[e], 0.0f), v1 = fmaxf(c1[e], 0.0f);
+        if (h2_out && r < nr) {
+            h2_out[(r0 + r) * HID + n0 + m] = v0;
+            h2_out[(r0 + r) * HID + n0 + 32 + m] = v1;
+        }
+        // sum over the wave's 64 columns of row r, in a fixed butterfly order
+        float v = v0 * w0 + v1 * w1;
+        for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (m == 0) red[wv][r] = v;
     }
     __syncthreads();
-    if (j < nr) z_out[r0 + j] = ((red[0][j] + red[1][j]) + (red[2][j] + red[3][j])) + p[OFF_B3];
+    if (t < nr) z_out[r0 + t] = ((red[0][t] + red[1][t]) + (red[2][t] + red[3][t])) + p[OFF_B3];
 }
 
 // ------------------------------------------------------------ backward --
@@ -141,7 +171,7 @@ __global__ __launch_bounds__(BLK) void backward_act_kernel(
     const bf16_t* __restrict__ w3, float* __restrict__ dz_out, float* __restrict__ da2_out,
     float* __restrict__ da1_out)
 {
-    __shared__ __align__(16) float d2[RB * HID];
+    __shared__ float d2[RB * HS];
     __shared__ float dzs[RB];
     const int j = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * RB;
@@ -160,29 +190,29 @@ __global__ __launch_bounds__(BLK) void backward_act_kernel(
     for (int r = 0; r < RB; ++r) {
         float d = 0.0f;
         if (r < nr && h2[(r0 + r) * HID + j] > 0.0f) d = dzs[r] * wj;
-        d2[r * HID + j] = d;
+        d2[r * HS + j] = d;
         if (r < nr) da2_out[(r0 + r) * HID + j] = d;
     }
     __syncthreads();
-    // thread k: sum_j da2[r][j] W2[j][k]
-    const int k = j;
-    float acc[RB];
+    // da2 [RB x HID] times W2 [HID (row j) x HID (column k)] on the matrix cores
+    const int l = j & 63, wv = j >> 6;
+    const int m = l & 31, h = l >> 5;
+    const int n0 = 64 * wv;
+    floatx16 c0, c1;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] = 0.0f;
-    for (int jj = 0; jj < HID; jj += 4) {
-        const float w0 = from_bf16(w2[(jj + 0) * HID + k]);
-        const float w1 = from_bf16(w2[(jj + 1) * HID + k]);
-        const float w2v = from_bf16(w2[(jj + 2) * HID + k]);
-        const float w3v = from_bf16(w2[(jj + 3) * HID + k]);
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const float4 d = *reinterpret_cast<const float4*>(d2 + r * HID + jj);
-            acc[r] = fmaf(d.x, w0, fmaf(d.y, w1, fmaf(d.z, w2v, fmaf(d.w, w3v, acc[r]))));
-        }
+    for (int e = 0; e < 16; ++e) {
+        c0[e] = 0.0f;
+        c1[e] = 0.0f;
     }
-    for (int r = 0; r < nr; ++r) {
-        const float a = h1[(r0 + r) * HID + k] > 0.0f ? acc[r] : 0.0f;
-        da1_out[(r0 + r) * HID + k] = a;
+    rows_times_weights<HID, HS>(d2, w2, n0, c0, c1);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int r = tile_row(e, h);
+        if (r < nr) {
+            const int64_t o = (r0 + r) * HID + n0 + m;
+            da1_out[o] = h1[o] > 0.0f ? c0[e] : 0.0f;
+            da1_out[o + 32] = h1[o + 32] > 0.0f ? c1[e] : 0.0f;
+        }
     }
 }
 
