@@ -89,7 +89,12 @@ typedef enum {
     NR_METHOD_CELLRUN = 3, /* fused; each lane takes the samples of one visit of the
                              time series to one grid cell (found by binary search on
                              the monotone cell index), so lanes never change cell
-                             inside a run and flush together */
+                             inside a run and flush together.
+                             The fused methods take instances whose heterodyne phase
+                             spans fewer than 2^30 phase-table steps (1024 per cycle in
+                             FP32, 256 in FP64: about 1e6 and 4e6 cycles of the band
+                             centre over the segment); longer spans, and instances
+                             whose tau needs the log1p/expm1 form, use NR_METHOD_STAGED */
     NR_METHOD_DIRECT = 4  /* baseline: the plain non-uniform DFT on the GPU, every
                              (sample, bin) term, no spreading and no FFT; never
                              chosen automatically; its segment sums need the plan's
@@ -127,7 +132,11 @@ typedef struct {
     int32_t method;             /* nr_method */
     double sigma;               /* grid upsampling factor in [1.25, 4]; <= 0: 2.0 */
     int32_t strain_complex;     /* 0: real strain; 1: interleaved complex (re, im) */
-    int32_t strict;             /* 1: unattainable tolerances are errors, not clamped */
+    int32_t strict;             /* 1: unattainable tolerances are errors, not clamped: an FP32
+                                   tolerance below 1e-6 without NR_AUTO, an FP64 tolerance
+                                   below 1e-12, or one below 4x the error of the FP64
+                                   heterodyne phase, about 2 pi (degree + 3) 2^-53 times the
+                                   cycles of the band centre over the segment */
     int32_t check_finite;       /* 1: execute scans the strain and synchronises */
     int32_t parts;              /* waves per instance in the spreader: 1, 2, 4, 8 or 16
                                    (8 and 16 span 2 and 4 workgroups whose partial grids

@@ -267,7 +267,10 @@ struct Decoded {
 };
 
 // Heterodyned sample value c = x exp(-2 pi i sc / N), N = 2^B table entries:
-// sc = k + theta N / (2 pi), |theta| <= pi / N.
+// sc = k + theta N / (2 pi), |theta| <= pi / N.  Needs |sc| < 2^31, the
+// range of the 32-bit conversion of k that picks the table entry: the plan
+// gives instances whose phase spans 2^30 table steps or more to the staged
+// method, whose points carry the phase already reduced modulo one cycle.
 template <typename T, bool CPLX>
 __device__ __forceinline__ void heterodyne_scaled(double sc, T xr, T xi, const cpx<T>* tab, T& cr, T& ci)
 {

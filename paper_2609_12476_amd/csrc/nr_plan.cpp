@@ -393,6 +393,9 @@ constexpr double kCellRunMinDensity = 24.0;
 constexpr double kCellRunMinDensityLarge = 12.0;
 constexpr int64_t kLargePlanWaves = 4096;
 constexpr size_t kCellRunMaxSparseLds = kLdsBytes / 5;
+// Longest heterodyne phase span, in phase-table steps, of an instance on the
+// fused spreaders (half the range of their 32-bit table-step conversion).
+constexpr double kFusedMaxPhaseSteps = 1073741824.0;
 
 // Waves per instance when the whole plan has too few waves to fill the chip:
 // enough to bring the samples per lane down to about 64 (at most 16 waves).
@@ -622,22 +625,39 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
                                          " (lower n_bins or sigma)");
         // tau series of the instance (ndeg < 0: the log1p/expm1 form)
         const double df_i = t.df > 0.0 ? t.df : g.fs / (double)g.n_samples;
-        {
-            // the heterodyne phase, counted in phase-table steps (at most
-            // 1024 per cycle), must stay below 2^48: beyond that FP64 no
-            // longer resolves a sixteenth of a step
-            const long double span = h.beta == 0.0 ? h.c * (long double)(g.n_samples - 1)
-                                                    : h.a * (1.0L - powl(1.0L - (long double)h.y_max, 0.625L));
-            const double fc = t.f_lo + (double)(K / 2) * df_i;
-            if (std::fabs(fc) * (double)span * 1024.0 >= 281474976710656.0)
-                fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) +
-                                             ": heterodyne frequency x duration too large (over 2^38 cycles)");
-        }
         series.clear();
         int ndeg = 0;
+        double phase_steps = 0.0;   // heterodyne phase span in phase-table steps
         if (h.beta != 0.0) {
             const double f_ref = std::fabs(t.f_lo) + (double)K * df_i + df_i;
             ndeg = horner_series(h, f_ref, fp64 ? 1e-14 : 1e-11, series);
+        }
+        {
+            // The heterodyne phase fc dtau is evaluated in FP64: the tau
+            // series (or log1p/expm1) and the product with fc each add a few
+            // units in the last place, so the phase in cycles carries a
+            // relative error of about (degree + 3) 2^-53, which grows with
+            // the cycles the segment spans.  An instance whose phase error
+            // would exceed a quarter of its tolerance cannot reach it in any
+            // precision class: an error in strict plans (otherwise the
+            // phase error bounds what the instance attains).  Counted in phase-table steps (at most 1024
+            // per cycle) the phase must also stay below 2^48, inside the
+            // range of the kernels' rounding to the nearest step.
+            const long double span = h.beta == 0.0 ? h.c * (long double)(g.n_samples - 1)
+                                                    : h.a * (1.0L - powl(1.0L - (long double)h.y_max, 0.625L));
+            const double fc = t.f_lo + (double)(K / 2) * df_i;
+            const double cycles = std::fabs(fc) * (double)span;
+            phase_steps = cycles * (double)phase_table_size(fp64);
+            if (cycles * 1024.0 >= 281474976710656.0)
+                fail(NR_ERR_INVALID_ARG, "instance " + std::to_string(i) +
+                                             ": heterodyne frequency x duration too large (over 2^38 cycles)");
+            const double terms = (ndeg > 0 ? ndeg : ndeg == 0 ? 1 : 8) + 3;
+            const double phase_err = 2.0 * M_PI * cycles * terms * 0x1p-53;
+            if (o.strict && phase_err > 0.25 * tol_eff)
+                fail(NR_ERR_TOL_UNATTAINABLE,
+                     "instance " + std::to_string(i) + ": the FP64 heterodyne phase over " +
+                         std::to_string(cycles) + " cycles is accurate to about " + std::to_string(phase_err) +
+                         " rad, too coarse for tolerance " + std::to_string(tol_eff));
         }
         int method = resolve_method(o.method);
         if (o.method == NR_METHOD_AUTO &&
@@ -662,6 +682,10 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         // form of tau; instances that need log1p/expm1 get their points from
         // the tau kernel
         if (ndeg < 0) method = NR_METHOD_STAGED;
+        // the fused spreaders pick the phase-table entry through a 32-bit
+        // conversion of the phase in table steps; longer phase spans take the
+        // staged path, whose tau kernel reduces the phase modulo one cycle
+        if (phase_steps >= kFusedMaxPhaseSteps && method != NR_METHOD_DIRECT) method = NR_METHOD_STAGED;
         if (method == NR_METHOD_CELLRUN) snap = 0;  // moments restart with every run
         ClassKey key{fp64, w, n, parts, method, flush, snap};
         size_t ci;

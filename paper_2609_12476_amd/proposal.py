@@ -1,255 +1,242 @@
-"""Learned proposal: rank coarse (chirp-mass cell, sub-band) regions for
-refinement on a finer chirp-mass grid.
+"""Learned proposal: rank coarse (chirp-mass cell, sub-band) regions and
+refine the best ones on a finer chirp-mass grid.
 
-Pipeline (every numeric step runs in the gfx950 library; torch provides
-device buffers, the random draws of the synthetic inputs and the top-k
-selection bookkeeping):
+ctypes binding of include/nr_proposal.h (``nr_prop_max_z``, ``nr_prop_topk``)
+plus the host orchestration of the pipeline.  Every numeric step runs in the
+gfx950 library; the host builds plans, moves the k selected region indices
+to the host to plan their refinement, and keeps torch buffers:
 
-  coarse grid   n_mc chirp masses log-spaced over [5e-4, 1e-1] Msun x 20 one-hertz
-                sub-bands (f0 at the centre), 120 segments of 30 s at 256 Hz;
-                semicoherent_sum gives S[template][bin] and N_used.
-  features      nr_mlp_region_features: 8 neighbouring chirp masses x 8 bins
-                around the template's loudest bin, z = (S/(L sigma^2) - N)/sqrt(N).
-  network       64-256-256-1 (nr_mlp_*), trained with BCE + Adam on
-                injections the pipeline generates, against noise-only draws.
-  refinement    the top-k regions' fine templates (8 per coarse cell,
-                log-spaced inside the cell) are searched; the exhaustive fine
-                grid is the fallback and the reference it is scored against.
-
-Region and label convention: a region is (coarse cell m, sub-band b); an
-injection (Mc, f) belongs to the region whose cell contains
-Mc* = Mc (f / f0_b)^{8/5}, f0_b the centre of the sub-band holding f, since
-beta(f0_b, Mc*) = beta(f, Mc) (Eq. (beta)): the template with that beta at
-f0_b resamples the chirp exactly.
+  coarse        semicoherent_sum over n_mc chirp masses x n_sub sub-bands
+                (Sec. III.C) gives S[template][bin] and N_used;
+  features      nr_mlp_region_features: z of the 8 neighbouring chirp masses
+                x 8 bins around each template's loudest bin;
+  network       nr_mlp_forward (64-256-256-1, trained with nr_mlp_train_step
+                on injections the method generates);
+  top-k         nr_prop_topk on the logits (ties to the lower region);
+  refine        semicoherent_sum over the selected regions' fine chirp masses
+                (per_cell per coarse cell), then nr_prop_max_z per region.
+The non-learned ranking takes nr_prop_max_z of each coarse template instead
+of the logits; the exhaustive fine grid (every region refined) is the
+fallback and the reference the ranking is judged against.
 """
 from __future__ import annotations
 
-import math
-from dataclasses import dataclass
+import ctypes
+from ctypes import c_char_p, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
 
+from synth.proposal import Grid, Layout, templates
+
 from . import nufft_resample as nr
-from .mlp import Mlp, nr_mlp_region_features
+from .mlp import nr_mlp_region_features
 
-MC_MIN, MC_MAX = 5e-4, 1e-1
-BAND_LO, N_SUB = 40.0, 20
-FS, T_COH, N_SEG = 256.0, 30.0, 120
-L_SEG = int(FS * T_COH)
 WORKSPACE = 96 << 30     # device workspace cap of the proposal plans (many draws at once)
-T_SUN = 1.3271244e20 / 299792458.0 ** 3
+
+SIGNATURES = {
+    "nr_prop_max_z": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, c_int32, c_double, c_void_p,
+                                c_void_p, c_void_p]),
+    "nr_prop_topk": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p, c_void_p]),
+    "nr_prop_last_error": (c_char_p, []),
+}
+_bound = False
 
 
-def beta_of(mc, f0):
-    return (96.0 / 5.0) * math.pi ** (8.0 / 3.0) * (T_SUN * mc) ** (5.0 / 3.0) * f0 ** (8.0 / 3.0)
+def lib():
+    global _bound
+    L = nr.load()
+    if not _bound:
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _bound = True
+    return L
 
 
-@dataclass
-class Grid:
-    """Coarse chirp-mass grid: n_mc cell centres log-spaced over the range; cell m spans
-    [edge_m, edge_{m+1}) with edges half a log step from the centres (clipped to the range)."""
-    n_mc: int
-
-    @property
-    def log_step(self):
-        return math.log(MC_MAX / MC_MIN) / (self.n_mc - 1)
-
-    def centres(self):
-        return MC_MIN * np.exp(self.log_step * np.arange(self.n_mc))
-
-    def cell_of(self, mc):
-        return np.clip(np.floor(np.log(np.asarray(mc) / MC_MIN) / self.log_step + 0.5), 0,
-                       self.n_mc - 1).astype(np.int64)
-
-    def cell_bounds(self, m):
-        lo = MC_MIN * math.exp(self.log_step * (m - 0.5))
-        hi = MC_MIN * math.exp(self.log_step * (m + 0.5))
-        return max(lo, MC_MIN), min(hi, MC_MAX)
-
-    def fine(self, m, per_cell=8):
-        """per_cell fine chirp masses log-spaced inside cell m (cell-centred)."""
-        lo, hi = self.cell_bounds(m)
-        q = (np.arange(per_cell) + 0.5) / per_cell
-        return lo * (hi / lo) ** q
+def _check(code):
+    if code != 0:
+        msg = lib().nr_prop_last_error()
+        raise nr.NrError(code, msg.decode() if msg else "")
 
 
-def region_of(grid, mc, f):
-    """(cell, sub-band) of an injection (Mc, f at t0)."""
-    b = np.clip(np.floor(np.asarray(f) - BAND_LO), 0, N_SUB - 1).astype(np.int64)
-    f0 = BAND_LO + b + 0.5
-    mc_star = np.asarray(mc) * (np.asarray(f) / f0) ** (8.0 / 5.0)
-    return grid.cell_of(mc_star), b
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
 
 
-# ----------------------------------------------------------------------------
-# Synthetic draws on the GPU (inputs, not part of the resampling arithmetic)
-# ----------------------------------------------------------------------------
-
-def chirp_waveform(t, mc, f, phi0, dtype):
-    """Unit-amplitude 0PN chirp cos(Phi) per draw: Phi of Eq. (phi) relative to t0,
-    zero past coalescence or above 0.45 fs.  t [N] (s), mc/f/phi0 [D] tensors."""
+def _stream(stream):
     import torch
-    b = beta_of_t(mc, f)[:, None]
-    y = (8.0 / 3.0) * b * t[None, :]
-    ok = y < 1.0
-    u = torch.clamp(1.0 - y, min=1e-300)
-    ph = (6.0 * math.pi / 5.0) * (f[:, None] / b) * (-torch.expm1(0.625 * torch.log(u))) + phi0[:, None]
-    fr = f[:, None] * u ** (-0.375)
-    ok &= fr <= 0.45 * FS
-    return torch.where(ok, torch.cos(ph), torch.zeros_like(ph)).to(dtype)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_void_p(s.cuda_stream)
 
 
-def beta_of_t(mc, f0):
-    return (96.0 / 5.0) * math.pi ** (8.0 / 3.0) * (T_SUN * mc) ** (5.0 / 3.0) * f0 ** (8.0 / 3.0)
-
-
-def draw_injections(gen, regions, grid, snr_lo=4.0, snr_hi=20.0):
-    """Injection parameters placed in the given (cell, sub-band) regions: f uniform in the
-    sub-band, Mc* log-uniform in the cell, Mc = Mc* (f0_b/f)^{8/5}, phi0 uniform, SNR uniform."""
+def _need(t, dtype, n, what):
     import torch
-    dev = gen.device
-    m, b = regions
-    D = len(m)
-    u = torch.rand(D, 4, generator=gen, device=dev, dtype=torch.float64)
-    f = BAND_LO + torch.as_tensor(b, device=dev, dtype=torch.float64) + u[:, 0]
-    lo = torch.as_tensor([grid.cell_bounds(int(mm))[0] for mm in m], device=dev, dtype=torch.float64)
-    hi = torch.as_tensor([grid.cell_bounds(int(mm))[1] for mm in m], device=dev, dtype=torch.float64)
-    mc_star = lo * (hi / lo) ** u[:, 1]
-    f0 = BAND_LO + torch.as_tensor(b, device=dev, dtype=torch.float64) + 0.5
-    mc = mc_star * (f0 / f) ** (8.0 / 5.0)
-    phi0 = 2.0 * math.pi * u[:, 2]
-    snr = snr_lo + (snr_hi - snr_lo) * u[:, 3]
-    return mc, f, phi0, snr
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous {dtype} CUDA tensor")
+    if t.numel() < n:
+        raise ValueError(f"{what} needs {n} values, has {t.numel()}")
 
 
-def make_strain(gen, D, inj=None, dtype=None):
-    """D draws of 1 h N(0,1) noise [D][N_SEG*L_SEG], plus the injections (Mc, f, phi0, snr)
-    scaled to their optimal SNR (white noise: rho^2 = sum h^2)."""
+def nr_prop_max_z(stat, n_used, n_groups, group, K, norm, zmax=None, arg=None, stream=None):
+    """(zmax [n_groups] float32, arg [n_groups] int32 or None): the largest z of each
+    run of `group` templates (device tensors)."""
     import torch
-    dtype = dtype or torch.float32
-    dev = gen.device
-    N = N_SEG * L_SEG
-    x = torch.randn(D, N, generator=gen, device=dev, dtype=dtype)
-    if inj is not None:
-        mc, f, phi0, snr = inj
-        t = torch.arange(N, device=dev, dtype=torch.float64) / FS
-        for i0 in range(0, D, 64):
-            i1 = min(D, i0 + 64)
-            h = chirp_waveform(t, mc[i0:i1], f[i0:i1], phi0[i0:i1], torch.float64)
-            e = torch.sqrt(torch.clamp((h * h).sum(dim=1), min=1e-300))
-            x[i0:i1] += (h * (snr[i0:i1] / e)[:, None]).to(dtype)
-    return x
+    _need(stat, torch.float32, n_groups * group * K, "stat")
+    _need(n_used, torch.int32, n_groups * group, "n_used")
+    if zmax is None:
+        zmax = torch.empty(n_groups, dtype=torch.float32, device=stat.device)
+    _need(zmax, torch.float32, n_groups, "zmax")
+    if arg is not None:
+        _need(arg, torch.int32, n_groups, "arg")
+    _check(lib().nr_prop_max_z(_ptr(stat), _ptr(n_used), int(n_groups), int(group), int(K), float(norm),
+                               _ptr(zmax), _ptr(arg), _stream(stream)))
+    return zmax, arg
+
+
+def nr_prop_topk(scores, rows, n, k, idx=None, stream=None):
+    """idx [rows][k] int32: the k best items of each row of scores [rows][n] (device)."""
+    import torch
+    _need(scores, torch.float32, rows * n, "scores")
+    if idx is None:
+        idx = torch.empty(rows, k, dtype=torch.int32, device=scores.device)
+    _need(idx, torch.int32, rows * k, "idx")
+    _check(lib().nr_prop_topk(_ptr(scores), int(rows), int(n), int(k), _ptr(idx), _stream(stream)))
+    return idx
 
 
 # ----------------------------------------------------------------------------
-# Plans
+# Plans over D draws of a layout (draw d owns strain [d * samples, (d + 1) * samples))
 # ----------------------------------------------------------------------------
 
-def _segments(D):
-    off = (np.arange(D)[:, None] * (N_SEG * L_SEG) + np.arange(N_SEG)[None, :] * L_SEG).ravel()
-    t = np.tile(np.arange(N_SEG) * T_COH, D)
-    return nr.make_segments(off, np.full(D * N_SEG, L_SEG), np.full(D * N_SEG, FS), t)
+def _segments(layout, D):
+    off = (np.arange(D)[:, None] * layout.samples + np.arange(layout.n_seg)[None, :] * layout.L).ravel()
+    t = np.tile(np.arange(layout.n_seg) * layout.t_coh, D)
+    return nr.make_segments(off, np.full(D * layout.n_seg, layout.L), np.full(D * layout.n_seg, layout.fs), t)
 
 
-def _templates(mcs, subbands):
-    mcs = np.asarray(mcs, np.float64)
-    b = np.asarray(subbands, np.float64)
-    n = len(mcs)
-    return nr.make_templates(mcs, BAND_LO + b + 0.5, BAND_LO + b, np.full(n, 1.0 / T_COH),
-                             np.full(n, 30, np.int32), np.full(n, BAND_LO + N_SUB))
+def _draw_plan(layout, mcs, subs, D, tol, kw):
+    """Plan of D draws x F templates per draw (mcs, subs [D][F]); template (d, f) at
+    d * F + f, instances of one template consecutive over its draw's segments."""
+    mcs = np.asarray(mcs, np.float64).reshape(D, -1)
+    subs = np.asarray(subs).reshape(D, -1)
+    F = mcs.shape[1]
+    S = layout.n_seg
+    seg = np.broadcast_to(np.arange(D)[:, None, None] * S + np.arange(S)[None, None, :], (D, F, S)).ravel()
+    tm = np.broadcast_to(np.arange(D * F).reshape(D, F)[:, :, None], (D, F, S)).ravel()
+    kw = dict(kw)
+    kw.setdefault("max_workspace_bytes", WORKSPACE)
+    return nr.Plan(_segments(layout, D), nr.make_templates(*templates(layout, mcs.ravel(), subs.ravel())),
+                   nr.make_instances(seg, tm), tol=tol, precision="fp32",
+                   strain_length=D * layout.samples, **kw), F
 
 
 class WindowPlan:
-    """D draw slots; slot d searches the 8-cell chirp-mass window around its region
-    (cells clamp(m-3..m+4) of sub-band b) over its own 120 segments.  Template (i, d)
-    is window position i of slot d, stored at i * D + d so the feature builder sees an
-    8 x D grid whose row 3 is each slot's own cell."""
+    """One slot per given region (m, b); slot d searches the 8-cell chirp-mass window
+    clamp(m-3..m+4) of sub-band b over its own draw.  Template (i, d) is window row i
+    of slot d, stored at i * D + d, so the feature builder sees an 8 x D grid whose
+    row 3 is each slot's own cell: the training features of the regions."""
 
-    def __init__(self, grid, regions, tol=1e-6, **kw):
+    def __init__(self, layout, grid, regions, tol=1e-6, **kw):
         m, b = (np.asarray(a) for a in regions)
         D = len(m)
-        centres = grid.centres()
         win = np.clip(m[None, :] + np.arange(-3, 5)[:, None], 0, grid.n_mc - 1)  # [8][D]
-        mcs = centres[win].ravel()
+        mcs = grid.centres()[win].ravel()
         subs = np.broadcast_to(b[None, :], (8, D)).ravel()
-        seg = (np.arange(D)[None, :, None] * N_SEG + np.arange(N_SEG)[None, None, :])
-        seg = np.broadcast_to(seg, (8, D, N_SEG)).ravel()
-        tm = np.broadcast_to((np.arange(8)[:, None] * D + np.arange(D)[None, :])[:, :, None],
-                             (8, D, N_SEG)).ravel()
-        inst = nr.make_instances(seg, tm)
-        self.D = D
+        S = layout.n_seg
+        seg = np.broadcast_to(np.arange(D)[None, :, None] * S + np.arange(S)[None, None, :], (8, D, S)).ravel()
+        tm = np.broadcast_to((np.arange(8)[:, None] * D + np.arange(D)[None, :])[:, :, None], (8, D, S)).ravel()
         kw.setdefault("max_workspace_bytes", WORKSPACE)
-        self.plan = nr.Plan(_segments(D), _templates(mcs, subs), inst, tol=tol, precision="fp32",
-                            strain_length=D * N_SEG * L_SEG, **kw)
+        self.layout, self.D = layout, D
+        self.plan = nr.Plan(_segments(layout, D), nr.make_templates(*templates(layout, mcs, subs)),
+                            nr.make_instances(seg, tm), tol=tol, precision="fp32",
+                            strain_length=D * layout.samples, **kw)
 
     def features(self, strain):
-        import torch
         stat, used = self.plan.semicoherent_sum(strain.view(-1))
-        f = nr_mlp_region_features(stat, used, 8, self.D, 30, 1.0 / L_SEG)
+        f = nr_mlp_region_features(stat, used, 8, self.D, self.layout.K, self.layout.norm)
         return f.view(8, self.D, 64)[3].contiguous(), stat, used
+
+    def close(self):
+        self.plan.close()
 
 
 class CoarsePlan:
-    """D draws x the whole coarse grid (n_mc cells x 20 sub-bands, template (m, b) of draw
-    d at (m * 20 + b) * D + d... laid out draw-minor so the feature builder runs per draw)."""
+    """D draws x the whole coarse grid: template (m, b) of draw d at
+    d * R + m * n_sub + b, R = n_mc * n_sub regions per draw."""
 
-    def __init__(self, grid, D, tol=1e-6, **kw):
-        centres = grid.centres()
-        n_t = grid.n_mc * N_SUB
-        mcs = np.repeat(centres, N_SUB)
-        subs = np.tile(np.arange(N_SUB), grid.n_mc)
-        # templates ordered draw-major: draw d owns templates [d * n_t, (d + 1) * n_t)
-        self.D, self.n_t, self.grid = D, n_t, grid
-        segs = _segments(D)
-        tmpls = _templates(np.tile(mcs, D), np.tile(subs, D))
-        seg = np.broadcast_to((np.arange(D)[:, None, None] * N_SEG + np.arange(N_SEG)[None, None, :]),
-                              (D, n_t, N_SEG)).ravel()
-        tm = np.broadcast_to((np.arange(D)[:, None] * n_t + np.arange(n_t)[None, :])[:, :, None],
-                             (D, n_t, N_SEG)).ravel()
-        kw.setdefault("max_workspace_bytes", WORKSPACE)
-        self.plan = nr.Plan(segs, tmpls, nr.make_instances(seg, tm), tol=tol, precision="fp32",
-                            strain_length=D * N_SEG * L_SEG, **kw)
+    def __init__(self, layout, grid, D, tol=1e-6, **kw):
+        R = grid.n_mc * layout.n_sub
+        mcs = np.tile(np.repeat(grid.centres(), layout.n_sub), D)
+        subs = np.tile(np.tile(np.arange(layout.n_sub), grid.n_mc), D)
+        self.layout, self.grid, self.D, self.R = layout, grid, D, R
+        self.plan, _ = _draw_plan(layout, mcs, subs, D, tol, kw)
 
     def run(self, strain):
-        """(features [D][n_t][64], stat [D][n_t][30], n_used [D][n_t])."""
+        """(features [D][R][64], stat [D * R * K], n_used [D * R])."""
         import torch
+        lay = self.layout
         stat, used = self.plan.semicoherent_sum(strain.view(-1))
-        feats = torch.empty(self.D, self.n_t, 64, dtype=torch.float32, device=strain.device)
+        feats = torch.empty(self.D, self.R, 64, dtype=torch.float32, device=strain.device)
+        step = self.R * lay.K
         for d in range(self.D):
-            nr_mlp_region_features(stat[d * self.n_t * 30:(d + 1) * self.n_t * 30],
-                                   used[d * self.n_t:(d + 1) * self.n_t], self.grid.n_mc, N_SUB, 30,
-                                   1.0 / L_SEG, feats[d])
-        return feats, stat.view(self.D, self.n_t, 30), used.view(self.D, self.n_t)
+            nr_mlp_region_features(stat[d * step:(d + 1) * step], used[d * self.R:(d + 1) * self.R],
+                                   self.grid.n_mc, lay.n_sub, lay.K, lay.norm, feats[d])
+        return feats, stat, used
 
+    def max_z(self, stat, used):
+        """Largest z of each coarse template, [D][R] (the non-learned score)."""
+        z, _ = nr_prop_max_z(stat, used, self.D * self.R, 1, self.layout.K, self.layout.norm)
+        return z.view(self.D, self.R)
 
-def zstat(stat, used):
-    """Standardised summed power (S/(L sigma^2) - N)/sqrt(N) (0 where N = 0)."""
-    import torch
-    N = used.to(torch.float64)[..., None]
-    z = (stat.to(torch.float64) / L_SEG - N) / torch.sqrt(torch.clamp(N, min=1.0))
-    return torch.where(N > 0, z, torch.zeros_like(z))
+    def close(self):
+        self.plan.close()
 
 
 class FinePlan:
-    """D draws x an explicit list of fine templates per draw (same count F per draw)."""
+    """D draws x F fine templates per draw (mcs, subs [D][F]); max_z gives the largest
+    z of every group of `group` consecutive fine templates."""
 
-    def __init__(self, mcs, subs, D, tol=1e-6, **kw):
-        mcs = np.asarray(mcs).reshape(D, -1)
-        subs = np.asarray(subs).reshape(D, -1)
-        F = mcs.shape[1]
-        self.D, self.F = D, F
-        seg = np.broadcast_to((np.arange(D)[:, None, None] * N_SEG + np.arange(N_SEG)[None, None, :]),
-                              (D, F, N_SEG)).ravel()
-        tm = np.broadcast_to((np.arange(D * F)).reshape(D, F)[:, :, None], (D, F, N_SEG)).ravel()
-        kw.setdefault("max_workspace_bytes", WORKSPACE)
-        self.plan = nr.Plan(_segments(D), _templates(mcs.ravel(), subs.ravel()),
-                            nr.make_instances(seg, tm), tol=tol, precision="fp32",
-                            strain_length=D * N_SEG * L_SEG, **kw)
+    def __init__(self, layout, mcs, subs, D, tol=1e-6, **kw):
+        self.layout, self.D = layout, D
+        self.plan, self.F = _draw_plan(layout, mcs, subs, D, tol, kw)
 
-    def max_z(self, strain):
+    def max_z(self, strain, group=1):
         stat, used = self.plan.semicoherent_sum(strain.view(-1))
-        z = zstat(stat.view(self.D, self.F, 30), used.view(self.D, self.F))
-        return z.amax(dim=2)   # [D][F]
+        z, _ = nr_prop_max_z(stat, used, self.D * self.F // group, group, self.layout.K, self.layout.norm)
+        return z.view(self.D, self.F // group)
+
+    def close(self):
+        self.plan.close()
+
+
+def rank(net, feats, k):
+    """Top-k regions [D][k] (int32, device) of each draw by the network's logits."""
+    D, R = feats.shape[0], feats.shape[1]
+    logits = net.forward(feats.reshape(D * R, 64))
+    return nr_prop_topk(logits, D, R, k), logits.view(D, R)
+
+
+def rank_max_z(zc, k):
+    """Top-k regions [D][k] of each draw by the largest coarse z (the non-learned ranking)."""
+    D, R = zc.shape
+    return nr_prop_topk(zc.contiguous(), D, R, k)
+
+
+def refine(layout, grid, strain, top, per_cell=8, **kw):
+    """Best fine z [D][k] of each selected region: top [D][k] region indices
+    m * n_sub + b (device or host); strain [D][samples] (device)."""
+    import torch
+    sel = top.cpu().numpy() if isinstance(top, torch.Tensor) else np.asarray(top)
+    D, k = sel.shape
+    m, b = sel // layout.n_sub, sel % layout.n_sub
+    mcs = grid.fine_of_regions(m, per_cell).reshape(D, k * per_cell)
+    subs = np.repeat(b, per_cell, axis=1)
+    fp = FinePlan(layout, mcs, subs, D, **kw)
+    try:
+        return fp.max_z(strain, group=per_cell)
+    finally:
+        fp.close()
 
 
 def train(net, x, y, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
@@ -272,3 +259,7 @@ def train(net, x, y, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
         if log:
             log(f"epoch {ep}: loss {hist[-1]:.4f}")
     return hist
+
+
+__all__ = ["Grid", "Layout", "WindowPlan", "CoarsePlan", "FinePlan", "nr_prop_max_z", "nr_prop_topk", "rank",
+           "rank_max_z", "refine", "train"]

@@ -198,13 +198,24 @@ def test_ragged_batch_grouped_launches(gpu):
         S = stat.cpu().numpy().astype(np.float64)
         used = used.cpu().numpy()
     assert np.array_equal(valid.cpu().numpy(), ok) and np.array_equal(used, used_r)
-    errs = per_instance_errors(X, Xr, off, ok)
-    say(f"  spectra max rel {errs.max():.3e}")
-    assert errs.max() <= max(FP32_SPEC, float(w.inst_tol.max()))
+    # each instance against its own tolerance (FP32 classes: at least 1e-5)
+    worst = 0.0
+    for i in range(w.n_inst):
+        if not ok[i]:
+            assert not np.any(X[off[i]:off[i + 1]]), f"invalid instance {i} not zero"
+            continue
+        t = float(w.inst_tol[i])
+        e = rel(X[off[i]:off[i + 1]], Xr[off[i]:off[i + 1]])
+        worst = max(worst, e / max(t, FP32_SPEC))
+        assert e <= max(t, FP32_SPEC), (i, t, e)
+    say(f"  spectra worst error / bound {worst:.3e}")
+    # a one-instance template's sum is that instance's power, whose relative
+    # error is at most about twice the spectrum's
     for m in range(len(soff) - 1):
         if used_r[m]:
+            t = float(w.inst_tol[m])
             e = rel(S[soff[m]:soff[m + 1]], Sr[soff[m]:soff[m + 1]])
-            assert e <= max(FP32_SUM, 10 * float(w.inst_tol[m])), (m, e)
+            assert e <= (FP32_SUM if t <= 1e-6 else max(FP32_SUM, 3 * t)), (m, t, e)
 
 
 def test_classes_sharing_templates(gpu):
@@ -414,3 +425,48 @@ def test_forced_flush_period(gpu, flush):
     assert cls[0].flush_period == flush
     errs = per_instance_errors(X, Xr, off, ok)
     assert errs.max() <= FP64_SPEC
+
+
+# ------------------------------------------------------- long phase spans --
+
+@pytest.mark.parametrize("method", ["fused", "cellrun", "staged"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_heterodyne_phase_beyond_2p31_steps(gpu, method, prec):
+    """A band centre of 10 kHz over a 1024 s segment spans about 1e7 cycles of
+    the heterodyne phase: 1e10 phase-table steps in FP32 (1024 per cycle) and
+    2.6e9 in FP64 (256 per cycle), past the 2^31 range of the fused spreaders'
+    table-step conversion.  Whatever method is asked for, the plan must run such
+    an instance on the staged path (phase reduced modulo one cycle) and match the
+    oracle's long-double reduction."""
+    say(f"phase beyond 2^31 steps {method} {prec}")
+    L, fs = 65536, 64.0
+    w = synth.random_small(31, L, 30, 1e-3, f0=50.0, fs=fs, f_lo=10000.0, df=fs / L)
+    fc = 10000.0 + 15 * fs / L
+    steps = fc * L / fs * (1024 if prec == "fp32" else 256)
+    assert steps > 2.0 ** 31
+    Xr, off, ok = oracle.spectra(w)
+    assert ok[0]
+    X, _, valid, _, cls = run_plan(w, gpu, precision=prec, method=method, tol=1e-6)
+    assert valid[0] == 1
+    assert [c.method for c in cls] == [1]          # NR_METHOD_STAGED
+    e = rel(X, Xr)
+    say(f"  rel l2 {e:.3e}")
+    assert e <= (FP32_SPEC if prec == "fp32" else 1e-6)
+
+
+@pytest.mark.parametrize("method", ["fused", "cellrun"])
+def test_heterodyne_phase_just_inside_fused_range(gpu, method):
+    """Just below 2^30 table steps (about 1e6 cycles in FP32) the fused spreaders
+    keep the instance and match the oracle."""
+    say(f"phase inside fused range {method}")
+    L, fs = 65536, 64.0
+    f_lo = 900.0                                   # ~9.2e5 cycles over 1024 s: 9.4e8 steps
+    w = synth.random_small(32, L, 30, 1e-3, f0=50.0, fs=fs, f_lo=f_lo, df=fs / L)
+    steps = (f_lo + 15 * fs / L) * L / fs * 1024
+    assert 2.0 ** 29 < steps < 2.0 ** 30
+    Xr, off, ok = oracle.spectra(w)
+    X, _, valid, _, cls = run_plan(w, gpu, precision="fp32", method=method, tol=1e-6)
+    assert [c.method for c in cls] == [2 if method == "fused" else 3]
+    e = rel(X, Xr)
+    say(f"  rel l2 {e:.3e}")
+    assert e <= FP32_SPEC

@@ -29,7 +29,7 @@ def declared_functions():
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         for m in re.finditer(r"\b([a-z_][a-z0-9_]*)\s*\(", src):
             name = m.group(1)
-            if name.startswith(("nufft_resample_", "nr_mlp_", "nr_ss_", "nr_strobo_")):
+            if name.startswith(("nufft_resample_", "nr_mlp_", "nr_ss_", "nr_strobo_", "nr_prop_")):
                 names.add(name)
     return names
 
@@ -39,6 +39,7 @@ def test_library_loads_and_exports_every_declared_symbol():
     names = declared_functions()
     assert "nufft_resample_plan" in names and "nufft_resample_execute" in names
     assert "nr_ss_create" in names and "nr_mlp_create" in names
+    assert "nr_prop_topk" in names and "nr_prop_max_z" in names
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
@@ -195,3 +196,43 @@ def test_stackslide_rejects_bad_arguments(case):
     assert code == nr.NR_ERR_INVALID_ARG
     assert not h.value
     assert lib.nr_ss_last_error(None)
+
+
+@pytest.mark.parametrize("case", ["topk_n0", "topk_k0", "topk_k_gt_n", "topk_n_big", "topk_null",
+                                  "maxz_group0", "maxz_group_big", "maxz_K0", "maxz_norm", "maxz_null"])
+def test_proposal_steps_reject_bad_arguments(case):
+    """nr_prop_topk / nr_prop_max_z validate their sizes and pointers before any launch;
+    empty work (zero rows or groups) is a no-op that succeeds."""
+    from paper_2609_12476_amd import proposal as pp
+    lib = pp.lib()
+    fake = ctypes.c_void_p(4096)       # never dereferenced: every case fails validation
+    if case.startswith("topk"):
+        rows, n, k, ptr = 3, 100, 10, fake
+        if case == "topk_n0":
+            n = 0
+        elif case == "topk_k0":
+            k = 0
+        elif case == "topk_k_gt_n":
+            k = 101
+        elif case == "topk_n_big":
+            n = 16385
+        elif case == "topk_null":
+            ptr = None
+        code = lib.nr_prop_topk(ptr, rows, n, k, ptr, None)
+        assert lib.nr_prop_topk(None, 0, 100, 10, None, None) == nr.NR_OK
+    else:
+        groups, group, K, norm, ptr = 3, 8, 30, 1.0 / 7680, fake
+        if case == "maxz_group0":
+            group = 0
+        elif case == "maxz_group_big":
+            group = 65
+        elif case == "maxz_K0":
+            K = 0
+        elif case == "maxz_norm":
+            norm = float("nan")
+        elif case == "maxz_null":
+            ptr = None
+        code = lib.nr_prop_max_z(ptr, ptr, groups, group, K, norm, ptr, None, None)
+        assert lib.nr_prop_max_z(None, None, 0, 8, 30, 1.0, None, None, None) == nr.NR_OK
+    assert code == nr.NR_ERR_INVALID_ARG
+    assert lib.nr_prop_last_error()
