@@ -52,6 +52,15 @@ nr_status nr_mlp_set_params(nr_mlp m, const float* host_params);
 /* Copy the masters to NR_MLP_PARAMS host floats (synchronous). */
 nr_status nr_mlp_get_params(nr_mlp m, float* host_params);
 
+/* Training state for checkpoint and resume: the masters, both Adam moment
+ * vectors and the Adam step count.  get copies them to the host (synchronous):
+ * state[3 * NR_MLP_PARAMS] = masters, first moments, second moments; *step =
+ * updates taken.  set restores them (and refreshes the bfloat16 copies), so a
+ * network resumed from a saved state continues training exactly as the
+ * original would have.  step >= 0. */
+nr_status nr_mlp_get_state(nr_mlp m, float* host_state, int64_t* step);
+nr_status nr_mlp_set_state(nr_mlp m, const float* host_state, int64_t step);
+
 /* logits[B] = network(x[B][64]) (device pointers, 1 <= B <= max_batch). */
 nr_status nr_mlp_forward(nr_mlp m, const float* x, int64_t B, float* logits);
 

@@ -491,6 +491,33 @@ nr_status nr_mlp_get_params(nr_mlp m, float* host_params)
     return st;
 }
 
+nr_status nr_mlp_get_state(nr_mlp m, float* host_state, int64_t* step)
+{
+    if (!m || !host_state || !step) return NR_ERR_INVALID_ARG;
+    const size_t b = NP * sizeof(float);
+    nr_status st = hip_status(m, hipMemcpyAsync(host_state, m->p, b, hipMemcpyDeviceToHost, m->stream), "state");
+    if (st == NR_OK) st = hip_status(m, hipMemcpyAsync(host_state + NP, m->m, b, hipMemcpyDeviceToHost, m->stream), "state");
+    if (st == NR_OK)
+        st = hip_status(m, hipMemcpyAsync(host_state + 2 * NP, m->v, b, hipMemcpyDeviceToHost, m->stream), "state");
+    if (st == NR_OK) st = hip_status(m, hipStreamSynchronize(m->stream), "state");
+    if (st == NR_OK) *step = m->step;
+    return st;
+}
+
+nr_status nr_mlp_set_state(nr_mlp m, const float* host_state, int64_t step)
+{
+    if (!m || !host_state || step < 0) return NR_ERR_INVALID_ARG;
+    const size_t b = NP * sizeof(float);
+    nr_status st = hip_status(m, hipMemcpyAsync(m->p, host_state, b, hipMemcpyHostToDevice, m->stream), "state");
+    if (st == NR_OK) st = hip_status(m, hipMemcpyAsync(m->m, host_state + NP, b, hipMemcpyHostToDevice, m->stream), "state");
+    if (st == NR_OK)
+        st = hip_status(m, hipMemcpyAsync(m->v, host_state + 2 * NP, b, hipMemcpyHostToDevice, m->stream), "state");
+    if (st == NR_OK) st = refresh(m);
+    if (st == NR_OK) st = hip_status(m, hipStreamSynchronize(m->stream), "state");
+    if (st == NR_OK) m->step = step;
+    return st;
+}
+
 nr_status nr_mlp_forward(nr_mlp m, const float* x, int64_t B, float* logits)
 {
     if (!m || !x || !logits) return NR_ERR_INVALID_ARG;

@@ -18,6 +18,8 @@ SIGNATURES = {
     "nr_mlp_create": (c_int32, [ctypes.POINTER(c_void_p), c_int64, c_void_p]),
     "nr_mlp_set_params": (c_int32, [c_void_p, c_void_p]),
     "nr_mlp_get_params": (c_int32, [c_void_p, c_void_p]),
+    "nr_mlp_get_state": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_int64)]),
+    "nr_mlp_set_state": (c_int32, [c_void_p, c_void_p, c_int64]),
     "nr_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
     "nr_mlp_gradient": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
     "nr_mlp_adam_step": (c_int32, [c_void_p, c_void_p, c_float]),
@@ -100,6 +102,35 @@ class Mlp:
         p = np.empty(N_PARAMS, np.float32)
         _check(lib().nr_mlp_get_params(self.handle, p.ctypes.data), self.handle)
         return p
+
+    def get_state(self):
+        """(state float32 [3 * N_PARAMS]: masters, Adam first and second moments; step)."""
+        st = np.empty(3 * N_PARAMS, np.float32)
+        step = c_int64()
+        _check(lib().nr_mlp_get_state(self.handle, st.ctypes.data, ctypes.byref(step)), self.handle)
+        return st, int(step.value)
+
+    def set_state(self, state, step):
+        st = np.ascontiguousarray(state, dtype=np.float32)
+        if st.size != 3 * N_PARAMS:
+            raise ValueError(f"expected {3 * N_PARAMS} state values")
+        _check(lib().nr_mlp_set_state(self.handle, st.ctypes.data, int(step)), self.handle)
+
+    def loss(self, x, y, out=None):
+        """Mean binary cross-entropy of x [N][64] against y [N] (device), over batches of at
+        most max_batch rows, as a device float64 scalar (no parameter changes)."""
+        import torch
+        N = x.shape[0]
+        _dev_f32(x, N * N_IN, "x")
+        _dev_f32(y, N, "y")
+        part = torch.empty(1, dtype=torch.float32, device=x.device)
+        tot = torch.zeros((), dtype=torch.float64, device=x.device) if out is None else out
+        for i0 in range(0, N, self.max_batch):
+            B = min(self.max_batch, N - i0)
+            _check(lib().nr_mlp_gradient(self.handle, _ptr(x[i0:i0 + B]), _ptr(y[i0:i0 + B]), B, None,
+                                         _ptr(part)), self.handle)
+            tot += part.double()[0] * (B / N)
+        return tot
 
     def forward(self, x, logits=None):
         import torch

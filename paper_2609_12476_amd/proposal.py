@@ -239,13 +239,17 @@ def refine(layout, grid, strain, top, per_cell=8, **kw):
         fp.close()
 
 
-def train(net, x, y, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
-    """Minibatch Adam on (x [N][64], y [N]) device tensors; returns the per-epoch mean loss."""
+def train(net, x, y, epochs=20, batch=1024, lr=1e-3, seed=0, log=None, val=None):
+    """Minibatch Adam on (x [N][64], y [N]) device tensors; returns the per-epoch mean
+    training loss.  val = (xv, yv): after every epoch the validation loss is taken
+    and the parameters of the epoch with the lowest one are kept (early stopping;
+    the network then holds them with fresh Adam moments); the per-epoch validation
+    losses are appended to the returned history as {"val": [...], "best_epoch": e}."""
     import torch
     g = torch.Generator(device="cpu").manual_seed(seed)
     N = x.shape[0]
     loss = torch.empty(1, dtype=torch.float32, device=x.device)
-    hist = []
+    hist, vhist, best = [], [], (float("inf"), -1, None)
     for ep in range(epochs):
         perm = torch.randperm(N, generator=g).to(x.device)
         tot = torch.zeros((), dtype=torch.float64, device=x.device)
@@ -256,8 +260,18 @@ def train(net, x, y, epochs=20, batch=1024, lr=1e-3, seed=0, log=None):
             tot += loss.double()[0]
             nb += 1
         hist.append(float(tot) / max(nb, 1))
+        msg = f"epoch {ep}: loss {hist[-1]:.4f}"
+        if val is not None:
+            vl = float(net.loss(*val))
+            vhist.append(vl)
+            msg += f", validation {vl:.4f}"
+            if vl < best[0]:
+                best = (vl, ep, net.get_params())
         if log:
-            log(f"epoch {ep}: loss {hist[-1]:.4f}")
+            log(msg)
+    if val is not None and best[2] is not None:
+        net.set_params(best[2])
+        return {"train": hist, "val": vhist, "best_epoch": best[1]}
     return hist
 
 

@@ -6,7 +6,8 @@ Steps (all on one GPU, every numeric step in the library's kernels):
   1. training set: one draw per coarse region per batch, half with an injection
      placed in that region (SNR uniform 4-20), half noise only; features from
      the 8-cell window around the region (WindowPlan).
-  2. train the network with minibatch Adam (nr_mlp_train_step).
+  2. train the network with minibatch Adam (nr_mlp_train_step), keeping the
+     epoch with the lowest loss on a held-back tenth of the examples.
   3. detection threshold: the (1 - 1e-2) quantile over noise-only draws of the
      exhaustive search's largest z over every fine template (FinePlan.max_z).
   4. held-out injections: blind coarse grid -> features -> logits -> top-k
@@ -15,9 +16,12 @@ Steps (all on one GPU, every numeric step in the library's kernels):
      region it refines within one cell of the true region (same sub-band)
      reaches the threshold with its best fine template; the exhaustive search
      refines every region.
-Reports, per k: the refined-grid cost k / regions, the missed-injection rate of
-each ranking, the extra misses against exhaustive search as a fraction of all
-held-out injections, and the fraction of the exhaustive search's detections
+Also the held-out discrimination of regions (ROC AUC on fresh windows, one
+injection and one noise draw per region) by the logits and by the region's
+own largest z.  Reports, per k: the refined-grid cost k / regions, the fraction of held-out
+injections whose true region (or a neighbouring cell) each ranking selects
+(recall), the missed-injection rate of each ranking, the extra misses against
+exhaustive search as a fraction of all held-out injections, and the fraction of the exhaustive search's detections
 each ranking loses (the figure the <= 1 % target is judged on, since the
 exhaustive search itself misses the faintest injections).
 """
@@ -35,8 +39,28 @@ def log(m):
     print(m, file=sys.stderr, flush=True)
 
 
+def roc_auc(score, label):
+    """Area under the ROC curve: the probability that a positive outranks a
+    negative (ties count one half), from the rank sum."""
+    score = np.asarray(score, np.float64)
+    label = np.asarray(label).astype(bool)
+    order = np.argsort(score, kind="stable")
+    ranks = np.empty(len(score))
+    s = score[order]
+    i = 0
+    while i < len(s):                       # average ranks over ties
+        j = i
+        while j + 1 < len(s) and s[j + 1] == s[i]:
+            j += 1
+        ranks[order[i:j + 1]] = 0.5 * (i + j) + 1.0
+        i = j + 1
+    n_pos, n_neg = label.sum(), (~label).sum()
+    return float((ranks[label].sum() - n_pos * (n_pos + 1) / 2) / (n_pos * n_neg))
+
+
 def run(scale=1.0, n_mc=256, per_cell=8, ks=(32, 128, 512), epochs=30, seed=1234, dev="cuda:0",
-        layout=None, judge_snr=(4.0, 20.0), batch_judge=16, thr_draws=None, quiet=False):
+        layout=None, judge_snr=(4.0, 20.0), batch_judge=16, thr_draws=None, n_train=None, n_judge=None,
+        quiet=False):
     import torch
 
     import synth
@@ -51,8 +75,8 @@ def run(scale=1.0, n_mc=256, per_cell=8, ks=(32, 128, 512), epochs=30, seed=1234
     gen = torch.Generator(device=dev).manual_seed(seed)
     grid = sp.Grid(n_mc)
     n_regions = n_mc * lay.n_sub
-    n_train = int(round(1e5 * scale))            # per class (injection / noise)
-    n_judge = int(round(2e4 * scale))
+    n_train = n_train or int(round(1e5 * scale))            # per class (injection / noise)
+    n_judge = n_judge or int(round(2e4 * scale))
     n_thr = thr_draws or max(100, int(round(1000 * scale)))
     out = {"layout": lay.__dict__, "n_mc_coarse": n_mc, "fine_per_cell": per_cell, "regions": n_regions,
            "train_per_class": n_train, "held_out_injections": n_judge, "threshold_noise_draws": n_thr,
@@ -85,15 +109,44 @@ def run(scale=1.0, n_mc=256, per_cell=8, ks=(32, 128, 512), epochs=30, seed=1234
     out["data_seconds"] = time.time() - t_start
 
     # --------------------------------------------------------------- 2. train
+    # a tenth of the examples is held back for early stopping
     net = Mlp(max_batch=1024, params=synth.mlp_init_params(seed))
+    untrained = Mlp(max_batch=1024, params=synth.mlp_init_params(seed))
+    order = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(seed)).to(X.device)
+    n_val = X.shape[0] // 10
+    Xv, Yv = X[order[:n_val]].contiguous(), Y[order[:n_val]].contiguous()
+    X, Y = X[order[n_val:]].contiguous(), Y[order[n_val:]].contiguous()
     t0 = time.time()
-    hist = pp.train(net, X, Y, epochs=epochs, batch=1024, lr=1e-3, seed=seed, log=say)
+    hist = pp.train(net, X, Y, epochs=epochs, batch=1024, lr=1e-3, seed=seed, log=say, val=(Xv, Yv))
     torch.cuda.synchronize()
     out["train_seconds"] = time.time() - t0
     out["loss_history"] = hist
     z = net.forward(X)
     out["train_accuracy"] = float(((z > 0).float() == Y).float().mean())
-    del X, Y
+    z = net.forward(Xv)
+    out["validation_accuracy"] = float(((z > 0).float() == Yv).float().mean())
+    del X, Y, Xv, Yv
+
+    # ------------------------------------------- held-out region discrimination
+    # fresh windows: every region once with an injection, once without; scores
+    # are the logits and, without the network, the region's own largest z (the
+    # patch's centre: its template at its loudest bin)
+    wp = pp.WindowPlan(lay, grid, (m_all, b_all))
+    sc_l, sc_u, sc_b, lab = [], [], [], []
+    for label in (1, 0):
+        inj = sp.draw_injections(gen, lay, grid, (m_all, b_all), *judge_snr) if label else None
+        f, _, _ = wp.features(sp.make_strain(gen, lay, n_regions, inj))
+        sc_l.append(net.forward(f).cpu().numpy())
+        sc_u.append(untrained.forward(f).cpu().numpy())
+        sc_b.append(f[:, 27].cpu().numpy())
+        lab.append(np.full(n_regions, label))
+    wp.close()
+    lab = np.concatenate(lab)
+    out["heldout_auc_learned"] = roc_auc(np.concatenate(sc_l), lab)
+    out["heldout_auc_max_z"] = roc_auc(np.concatenate(sc_b), lab)
+    out["heldout_auc_untrained"] = roc_auc(np.concatenate(sc_u), lab)
+    untrained.close()
+    say(f"held-out AUC: learned {out['heldout_auc_learned']:.4f}, max z {out['heldout_auc_max_z']:.4f}")
 
     # ----------------------------------------------------------- 3. threshold
     fine_mc = grid.fine_of_regions(np.arange(n_mc), per_cell).ravel()      # cell-major
@@ -118,6 +171,7 @@ def run(scale=1.0, n_mc=256, per_cell=8, ks=(32, 128, 512), epochs=30, seed=1234
     D_j = batch_judge
     cp = pp.CoarsePlan(lay, grid, D_j)
     det_exh, det_learn, det_base = [], {k: [] for k in ks}, {k: [] for k in ks}
+    rec_learn, rec_base = {k: [] for k in ks}, {k: [] for k in ks}
     t0 = time.time()
     for i0 in range(0, n_judge, D_j):
         reg = rng.choice(all_regions, size=D_j, replace=True)
@@ -136,8 +190,11 @@ def run(scale=1.0, n_mc=256, per_cell=8, ks=(32, 128, 512), epochs=30, seed=1234
             hit = fz[d] >= thr
             det_exh.append(bool(hit.any()))
             for k in ks:
-                det_learn[k].append(bool(np.any(hit & np.isin(nb_region[d], sel_l[k][d]))))
-                det_base[k].append(bool(np.any(hit & np.isin(nb_region[d], sel_b[k][d]))))
+                in_l, in_b = np.isin(nb_region[d], sel_l[k][d]), np.isin(nb_region[d], sel_b[k][d])
+                det_learn[k].append(bool(np.any(hit & in_l)))
+                det_base[k].append(bool(np.any(hit & in_b)))
+                rec_learn[k].append(bool(in_l.any()))
+                rec_base[k].append(bool(in_b.any()))
         del x
         if (i0 // D_j) % 50 == 0:
             say(f"judged {i0 + D_j}/{n_judge}")
@@ -158,7 +215,8 @@ def run(scale=1.0, n_mc=256, per_cell=8, ks=(32, 128, 512), epochs=30, seed=1234
             "extra_missed_learned": float(np.mean(exh & ~dl)),
             "extra_missed_baseline": float(np.mean(exh & ~db)),
             "lost_of_exhaustive_detections_learned": float(np.sum(exh & ~dl) / max(n_det, 1)),
-            "lost_of_exhaustive_detections_baseline": float(np.sum(exh & ~db) / max(n_det, 1))})
+            "lost_of_exhaustive_detections_baseline": float(np.sum(exh & ~db) / max(n_det, 1)),
+            "recall_learned": float(np.mean(rec_learn[k])), "recall_baseline": float(np.mean(rec_base[k]))})
     out["total_seconds"] = time.time() - t_start
     return out
 
@@ -171,8 +229,12 @@ def main():
     ap.add_argument("--n-mc", type=int, default=256)
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--snr-lo", type=float, default=4.0)
+    ap.add_argument("--n-train", type=int, default=None)
+    ap.add_argument("--n-judge", type=int, default=None)
+    ap.add_argument("--ks", default="32,128,512")
     args = ap.parse_args()
-    res = run(scale=args.scale, epochs=args.epochs, n_mc=args.n_mc, seed=args.seed, judge_snr=(args.snr_lo, 20.0))
+    res = run(scale=args.scale, epochs=args.epochs, n_mc=args.n_mc, seed=args.seed, judge_snr=(args.snr_lo, 20.0),
+              n_train=args.n_train, n_judge=args.n_judge, ks=tuple(int(k) for k in args.ks.split(",")))
     s = json.dumps(res)
     if args.out:
         with open(args.out, "w") as f:

@@ -118,26 +118,49 @@ def test_training_reduces_loss_on_separable_data(gpu):
     net.close()
 
 
-def test_region_features_match_definition(gpu):
+def test_region_features_match_oracle(gpu):
+    """nr_mlp_region_features against oracle.proposal.region_features on the same
+    float sums (every loudest bin is unique, so the patches agree exactly)."""
     say("region features")
     import torch
+    from oracle import proposal as op
     from paper_2609_12476_amd.mlp import nr_mlp_region_features
     rng = np.random.default_rng(11)
     n_mc, n_sub, K, L = 9, 3, 30, 7680
     stat = (rng.gamma(50.0, L, size=(n_mc * n_sub, K))).astype(np.float32)
     stat[4, 17] *= 3
+    stat[7, 0] *= 3                                # loudest bin at the band edges
+    stat[8, K - 1] *= 3
     used = rng.integers(0, 60, size=n_mc * n_sub).astype(np.int32)
     used[5] = 0
     f = nr_mlp_region_features(torch.from_numpy(stat.ravel()).to(gpu), torch.from_numpy(used).to(gpu),
                                n_mc, n_sub, K, 1.0 / L).cpu().numpy()
-    for region in range(n_mc * n_sub):
-        mc, sb = divmod(region, n_sub)
-        ks = int(np.argmax(stat[region]))
-        for i in range(8):
-            m2 = min(max(mc - 3 + i, 0), n_mc - 1)
-            tm = m2 * n_sub + sb
-            for c in range(8):
-                k = min(max(ks - 3 + c, 0), K - 1)
-                N = used[tm]
-                ref = 0.0 if N == 0 else (stat[tm, k] / L - N) / np.sqrt(N)
-                assert abs(f[region, 8 * i + c] - ref) <= 1e-5 * max(1.0, abs(ref))
+    ref = op.region_features(stat.astype(np.float64).ravel(), used, n_mc, n_sub, K, 1.0 / L)
+    assert np.allclose(f, ref, rtol=1e-5, atol=1e-5)
+
+
+def test_state_checkpoint_resumes_bitwise(gpu):
+    """Saving the masters, Adam moments and step count and restoring them into a
+    fresh network continues training bit for bit like the original."""
+    say("mlp state checkpoint")
+    import torch
+    from paper_2609_12476_amd.mlp import Mlp
+    x, y = _data(5, 256)
+    xd, yd = torch.from_numpy(x).to(gpu), torch.from_numpy(y).to(gpu)
+    a = Mlp(max_batch=256, params=synth.mlp_init_params(4))
+    for _ in range(3):
+        a.train_step(xd, yd, 1e-3)
+    state, step = a.get_state()
+    assert step == 3
+    for _ in range(2):
+        a.train_step(xd, yd, 1e-3)
+    b = Mlp(max_batch=256)
+    b.set_state(state, step)
+    for _ in range(2):
+        b.train_step(xd, yd, 1e-3)
+    assert np.array_equal(a.get_params(), b.get_params())
+    sa, na = a.get_state()
+    sb, nb = b.get_state()
+    assert na == nb == 5 and np.array_equal(sa, sb)
+    a.close()
+    b.close()
