@@ -258,6 +258,40 @@ nr_status nufft_resample_semicoherent_sum(nr_plan p, const void* strain,
                                           int32_t* n_used);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * segment sum of nufft_resample_semicoherent_sum for the plan that
+ * nufft_resample_plan would build from the same arguments, planned, run and
+ * released inside this one call without any device allocation.  Every
+ * device buffer of that plan (instance tables, the lane-major strain copy,
+ * grids, power rows) is carved from one static scratch array of
+ * NR_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends; no hipMalloc, hipFree, stream, event or graph is
+ * created.
+ *   segs ... opt: as for nufft_resample_plan, except that opt->profile,
+ *       opt->use_graph and opt->tune must be 0 (NR_ERR_INVALID_ARG), side
+ *       streams are not used, and grids, point stream and power rows are
+ *       budgeted within half the scratch (opt->max_workspace_bytes may only
+ *       lower that); opt may be NULL (defaults, null stream).
+ *   strain, seg_weight, stat, n_used: as for nufft_resample_semicoherent_sum
+ *       (device pointers; stat and n_used are accumulated into).
+ * The call synchronises opt->stream before planning (an earlier call on that
+ * stream may still read the scratch) and returns after the sum has
+ * completed.  Every call on one GPU shares that GPU's scratch, which keeps
+ * the last call's contents: calls that overlap on one GPU (from other host
+ * threads, or on other streams) race and must be serialised by the caller.
+ * NR_ERR_OUT_OF_MEMORY when the plan needs more than the scratch; other
+ * failures as for plan / semicoherent_sum, with the message in
+ * nufft_resample_last_error(NULL).
+ */
+#define NR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+nr_status nufft_resample_semicoherent_sum_static(const nr_segment* segs, int32_t n_segs,
+                                                 const nr_template* tmpls, int32_t n_tmpls,
+                                                 const nr_instance* inst, int64_t n_inst, double tol,
+                                                 const nr_options* opt, const void* strain,
+                                                 const double* seg_weight, void* stat, int32_t* n_used);
+
+/*
  * Per-stage kernel times of a plan created with profile = 1: waits for the
  * recorded launches to finish (synchronising), returns their summed
  * durations and starts a new accumulation.  All zeros when profiling is off.

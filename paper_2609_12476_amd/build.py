@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libnufft_resample.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["nr_kernels.hip", "nr_plan.cpp", "nr_params.cpp", "nr_mlp.hip", "nr_proposal.hip", "nr_stackslide.hip",
-           "nr_strobo.hip"]
+           "nr_strobo.hip", "nr_static.hip"]
 
 ARCH = "gfx950"
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

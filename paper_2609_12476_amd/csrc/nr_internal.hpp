@@ -2,8 +2,11 @@
 #pragma once
 
 #include <cstdint>
+#include <string>
 
 #include <hip/hip_runtime.h>
+
+#include "../../include/nufft_resample.h"
 
 namespace nr {
 
@@ -172,5 +175,17 @@ size_t spread_lds_bytes(int fp64, int n);
 int phase_table_size(int fp64);
 constexpr int kHornerPad = 16;   // zero coefficients appended to every class's tau series
 size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode);
+
+// Set the message of nufft_resample_last_error(NULL) on this thread; returns code.
+nr_status report_create_error(nr_status code, const std::string& msg);
+
+// Plan (every device buffer carved from [base, base + bytes)), segment sum and
+// release, with no device allocation; the arguments are those of
+// nufft_resample_plan and nufft_resample_semicoherent_sum.  Synchronises the
+// options' stream before and after.  Messages go to nufft_resample_last_error(NULL).
+nr_status semicoherent_sum_in_arena(void* base, size_t bytes, const nr_segment* segs, int32_t n_segs,
+                                    const nr_template* tmpls, int32_t n_tmpls, const nr_instance* inst,
+                                    int64_t n_inst, double tol, const nr_options* opt, const void* strain,
+                                    const double* seg_weight, void* stat, int32_t* n_used);
 
 }  // namespace nr

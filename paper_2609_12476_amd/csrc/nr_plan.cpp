@@ -41,24 +41,47 @@ void hip_check(hipError_t e, const char* what)
     if (e != hipSuccess) fail(NR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Device memory of the plans built on this thread: NULL for hipMalloc, else
+// a bump allocator over memory the caller provides (the static-scratch entry
+// point), from which buffers are carved and never freed.
+struct Arena {
+    char* base;
+    size_t size, used;
+};
+thread_local Arena* g_arena = nullptr;
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool owned = false;   // allocated with hipMalloc (else carved from an arena)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes)
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), owned(o.owned)
     {
         o.p = nullptr;
         o.bytes = 0;
+        o.owned = false;
     }
     ~DevBuf()
     {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
     }
     void alloc(size_t b, const char* what)
     {
         if (b == 0) b = 16;
+        if (g_arena) {
+            const size_t at = (g_arena->used + 255) & ~size_t(255);
+            if (at > g_arena->size || b > g_arena->size - at)
+                fail(NR_ERR_OUT_OF_MEMORY, std::string("the plan needs more than the ") +
+                                               std::to_string(g_arena->size) + "-byte static scratch (at " + what +
+                                               ": " + std::to_string(at + b) + " bytes)");
+            p = g_arena->base + at;
+            g_arena->used = at + b;
+            bytes = b;
+            owned = false;
+            return;
+        }
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             p = nullptr;
@@ -66,6 +89,7 @@ struct DevBuf {
                                            " bytes for " + what + " failed: " + hipGetErrorString(e));
         }
         bytes = b;
+        owned = true;
     }
     template <typename T>
     void upload(const std::vector<T>& v, const char* what)
@@ -907,7 +931,8 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         build_groups(P);
         P.n_chunks = (int)P.spread_groups.size();
         const size_t most = std::max(P.spread_groups.size(), P.epi_groups.size());
-        const int n_side = (int)std::min<size_t>(3, most > 0 ? most - 1 : 0);
+        // plans built in an arena create no streams or events
+        const int n_side = g_arena ? 0 : (int)std::min<size_t>(3, most > 0 ? most - 1 : 0);
         for (int i = 0; i < n_side; ++i) {
             hipStream_t st;
             hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "side stream");
@@ -1503,6 +1528,68 @@ nr_status guarded(nr_plan_s* P, F&& f)
 }
 
 }  // namespace
+
+namespace nr {
+
+nr_status report_create_error(nr_status code, const std::string& msg)
+{
+    g_create_error = msg;
+    return code;
+}
+
+nr_status semicoherent_sum_in_arena(void* base, size_t bytes, const nr_segment* segs, int32_t n_segs,
+                                    const nr_template* tmpls, int32_t n_tmpls, const nr_instance* inst,
+                                    int64_t n_inst, double tol, const nr_options* opt, const void* strain,
+                                    const double* seg_weight, void* stat, int32_t* n_used)
+{
+    nr_options o;
+    if (opt)
+        o = *opt;
+    else
+        nufft_resample_default_options(&o);
+    if (o.profile || o.use_graph || o.tune) {
+        g_create_error = "profile, use_graph and tune need device allocations: they must be 0 here";
+        return NR_ERR_INVALID_ARG;
+    }
+    if (!base || bytes < 4096) {
+        g_create_error = "no static scratch";
+        return NR_ERR_DEVICE;
+    }
+    // grids, point stream and power rows within half the scratch; the tables
+    // and the lane-major strain take the rest
+    const int64_t budget = (int64_t)(bytes / 2);
+    o.max_workspace_bytes = o.max_workspace_bytes > 0 ? std::min<int64_t>(o.max_workspace_bytes, budget) : budget;
+    const hipStream_t st = (hipStream_t)o.stream;
+    // a previous call on this stream may still read the scratch
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        g_create_error = std::string("stream synchronisation: ") + hipGetErrorString(e);
+        return NR_ERR_DEVICE;
+    }
+    std::unique_ptr<nr_plan_s> P;
+    try {
+        P.reset(new nr_plan_s());
+    } catch (...) {
+        g_create_error = "host allocation failed";
+        return NR_ERR_OUT_OF_MEMORY;
+    }
+    P->opt = o;
+    Arena arena{static_cast<char*>(base), bytes, 0};
+    g_arena = &arena;
+    nr_status s = guarded(P.get(), [&] { create_plan(*P, segs, n_segs, tmpls, n_tmpls, inst, n_inst, tol); });
+    g_arena = nullptr;
+    if (s == NR_OK) s = guarded(P.get(), [&] { semicoherent(*P, strain, seg_weight, stat, n_used); });
+    if (s != NR_OK) g_create_error = P->err;
+    // the sum reads the scratch: finish before it can be reused
+    e = hipStreamSynchronize(st);
+    if (s == NR_OK && e != hipSuccess) {
+        g_create_error = std::string("segment sum: ") + hipGetErrorString(e);
+        s = NR_ERR_DEVICE;
+    }
+    return s;
+}
+
+}  // namespace nr
 
 extern "C" {
 

@@ -81,6 +81,11 @@ SIGNATURES = {
     "nufft_resample_execute": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nufft_resample_semicoherent_sum": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p,
                                                   c_void_p]),
+    "nufft_resample_semicoherent_sum_static": (c_int32, [ctypes.POINTER(NrSegment), c_int32,
+                                                         ctypes.POINTER(NrTemplate), c_int32,
+                                                         ctypes.POINTER(NrInstance), c_int64, c_double,
+                                                         ctypes.POINTER(NrOptions), c_void_p, c_void_p,
+                                                         c_void_p, c_void_p]),
     "nufft_resample_query": (c_int32, [c_void_p, ctypes.POINTER(NrPlanInfo)]),
     "nufft_resample_stage_times": (c_int32, [c_void_p, ctypes.POINTER(NrStageTimes)]),
     "nufft_resample_query_class": (c_int32, [c_void_p, c_int32, ctypes.POINTER(NrClassInfo)]),
@@ -149,6 +154,17 @@ def nufft_resample_execute(plan, strain_ptr, spectra_ptr, power_ptr, valid_ptr):
 def nufft_resample_semicoherent_sum(plan, strain_ptr, weight_ptr, stat_ptr, n_used_ptr):
     _check(load().nufft_resample_semicoherent_sum(plan, strain_ptr, weight_ptr, stat_ptr,
                                                   n_used_ptr), plan)
+
+
+def nufft_resample_semicoherent_sum_static(segs, tmpls, inst, tol, opt, strain_ptr, weight_ptr, stat_ptr,
+                                           n_used_ptr):
+    """Plan, segment sum and release in one call without device allocation (the
+    library's static scratch); segs / tmpls / inst as for nufft_resample_plan."""
+    n_inst = len(inst) if inst is not None else 0
+    code = load().nufft_resample_semicoherent_sum_static(segs, len(segs), tmpls, len(tmpls), inst, n_inst,
+                                                         float(tol), ctypes.byref(opt) if opt is not None else None,
+                                                         strain_ptr, weight_ptr, stat_ptr, n_used_ptr)
+    _check(code, None)
 
 
 def nufft_resample_query(plan):
