@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-direct", action="store_true", help="skip the GPU direct-sum baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the beta-bank and ragged-512 keys")
     ap.add_argument("--cpu-sample", type=int, default=3072,
                     help="instances timed on the oracle (seeded sample)")
     ap.add_argument("--copy-mib", type=int, default=256,
@@ -125,8 +126,10 @@ def time_steps(plan, x, stat, used, steps, warmup):
     return t1 - t0, plan.stage_times()
 
 
-def other_workload(args, dev):
-    """Throughput of the non-headline workloads (one JSON line each)."""
+def measure_workload(args, dev, workload, steps, check=16, tune=False, method="auto"):
+    """Time one of the secondary workloads (HIP-graph replay), its spreader's
+    VALU fraction by the op model (a second, profiled plan) and a sampled
+    oracle check; returns the result dict."""
     import torch
 
     import oracle
@@ -134,37 +137,39 @@ def other_workload(args, dev):
     from paper_2609_12476_amd import Plan, complex_view
 
     stream = torch.cuda.Stream()
-    out = {"unit": "spectra/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic"}
+    out = {}
     with torch.cuda.stream(stream):
-        if args.workload == "ragged_512":
+        if workload == "ragged_512":
             w = synth.ragged_batch(n_inst=512, seed=2)
-            kw = dict(precision="auto", use_graph=True, tune=args.tune, method=args.method)
+            kw = dict(precision="auto", tune=tune, method=method)
             mode = "execute"
-        elif args.workload == "paper_beta_bank":
+        elif workload == "paper_beta_bank":
             w = synth.paper_bank(hours=1.0).as_float32_strain()
-            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune, method=args.method)
+            kw = dict(precision="fp32", tol=1e-6, tune=tune, method=method)
             mode = "execute"
         else:
             w = synth.semicoherent(hours=6.0, n_mc=2048, n_sub=20, seed=3, tol=1e-6).as_float32_strain()
-            kw = dict(precision="fp32", tol=1e-6, use_graph=True, tune=args.tune, method=args.method)
+            kw = dict(precision="fp32", tol=1e-6, tune=tune, method=method)
             mode = "sum"
         kw.update(flush_period=args.flush_period, moment_mode=args.moment_mode)
         log(f"{w.name}: planning {w.n_inst} instances")
         t0 = time.perf_counter()
-        plan = Plan.from_workload(w, stream=stream, **kw)
+        plan = Plan.from_workload(w, stream=stream, use_graph=True, **kw)
         plan_s = time.perf_counter() - t0
         x = plan.strain_tensor(w.strain, dev)
         info = plan.info
-        if mode == "execute":
-            sp = torch.empty(2 * info.total_bins, dtype=plan.out_dtype, device=dev)
-            pw = torch.empty(info.total_bins, dtype=plan.out_dtype, device=dev)
-            va = torch.empty(plan.n_inst, dtype=torch.uint8, device=dev)
-            step = lambda: plan.execute(x, sp, pw, va)
-        else:
-            st = torch.zeros(info.stat_bins, dtype=plan.out_dtype, device=dev)
-            us = torch.zeros(plan.n_tmpls, dtype=torch.int32, device=dev)
-            step = lambda: plan.semicoherent_sum(x, None, st, us)
-        steps = max(2, args.steps // (10 if mode == "sum" else 1))
+
+        def stepper(pl):
+            if mode == "execute":
+                sp = torch.empty(2 * info.total_bins, dtype=pl.out_dtype, device=dev)
+                pw = torch.empty(info.total_bins, dtype=pl.out_dtype, device=dev)
+                va = torch.empty(pl.n_inst, dtype=torch.uint8, device=dev)
+                return lambda: pl.execute(x, sp, pw, va)
+            st = torch.zeros(info.stat_bins, dtype=pl.out_dtype, device=dev)
+            us = torch.zeros(pl.n_tmpls, dtype=torch.int32, device=dev)
+            return lambda: pl.semicoherent_sum(x, None, st, us)
+
+        step = stepper(plan)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -174,26 +179,54 @@ def other_workload(args, dev):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         cls = plan.classes()
+        samples = int(sum(c.n_points for c in cls))
         out.update({"metric": f"{w.name} spectra/s", "value": info.n_valid * steps / el,
-                    "ms_per_step": el / steps * 1e3, "steps": steps, "warmup": args.warmup,
+                    "ms_per_step": el / steps * 1e3, "steps": steps, "samples_per_s": samples * steps / el,
                     "config": {"workload": w.name, "instances": int(info.n_inst), "valid": int(info.n_valid),
-                               "classes": len(cls), "chunks": int(info.n_chunks), "graph": True,
-                               "tuned": bool(args.tune), "plan_seconds": plan_s},
+                               "samples": samples, "classes": len(cls), "chunks": int(info.n_chunks),
+                               "graph": True, "tuned": bool(tune), "plan_seconds": plan_s},
                     "class_shapes": [(c.fp64, c.w, c.n, c.degree, c.parts, c.method, c.flush_period, c.n_inst)
                                      for c in cls]})
-        # sampled parity against the oracle
-        rng = np.random.default_rng(7)
-        ok = plan.valid_mask().astype(bool)
-        idx = np.sort(rng.choice(np.flatnonzero(ok), size=min(16, int(ok.sum())), replace=False))
-        sp2, _, _ = plan.execute(x, want=("spectra",))
+        # spreader time and VALU fraction from a profiled plan of the same workload
+        prof = Plan.from_workload(w, stream=stream, profile=True, **kw)
+        pstep = stepper(prof)
+        pstep()
         torch.cuda.synchronize()
-        X = complex_view(sp2).cpu().numpy().astype(np.complex128)
-        Xr, off, _ = oracle.spectra(w, inst_idx=idx)
-        boff = plan.bin_offsets()
-        errs = [np.linalg.norm(X[boff[i]:boff[i + 1]] - Xr[off[j]:off[j + 1]]) /
-                np.linalg.norm(Xr[off[j]:off[j + 1]]) for j, i in enumerate(idx)]
-        out["oracle_check"] = {"instances": len(idx), "spectra_rel_l2_max": float(np.max(errs))}
+        prof.stage_times()
+        for _ in range(steps):
+            pstep()
+        stt = prof.stage_times()
+        spread_ms = stt["spread"][0] / steps
+        if all(c.method in (2, 3) for c in cls):
+            ops = algorithmic_ops(cls)
+            out["spread_ms_per_step"] = spread_ms
+            out["spread_valu_frac"] = ops / (spread_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS
+            out["spread_valu_basis"] = "per-sample op model (algorithmic_ops) over the summed spread launches"
+        out["stage_ms_per_step"] = {k: v[0] / steps for k, v in stt.items()}
+        prof.close()
+        # sampled parity against the oracle
+        if check:
+            rng = np.random.default_rng(7)
+            ok = plan.valid_mask().astype(bool)
+            idx = np.sort(rng.choice(np.flatnonzero(ok), size=min(check, int(ok.sum())), replace=False))
+            sp2, _, _ = plan.execute(x, want=("spectra",))
+            torch.cuda.synchronize()
+            X = complex_view(sp2).cpu().numpy().astype(np.complex128)
+            Xr, off, _ = oracle.spectra(w, inst_idx=idx)
+            boff = plan.bin_offsets()
+            errs = [np.linalg.norm(X[boff[i]:boff[i + 1]] - Xr[off[j]:off[j + 1]]) /
+                    np.linalg.norm(Xr[off[j]:off[j + 1]]) for j, i in enumerate(idx)]
+            out["oracle_check"] = {"instances": len(idx), "spectra_rel_l2_max": float(np.max(errs))}
         plan.close()
+    return out
+
+
+def other_workload(args, dev):
+    """Throughput of the non-headline workloads (one JSON line each)."""
+    steps = max(2, args.steps // (10 if args.workload == "full_sweep_6h" else 1))
+    out = {"unit": "spectra/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "warmup": args.warmup}
+    out.update(measure_workload(args, dev, args.workload, steps, tune=args.tune, method=args.method))
     print(json.dumps(out), flush=True)
 
 
@@ -268,15 +301,45 @@ def stackslide_workload(args, dev):
     return out
 
 
-def copy_calibration(args, dev):
-    """One plain device copy of known size, for scaling the memory counters."""
+def copy_calibration(args, dev, reps=5):
+    """Plain device copies of known size (the memory counters of one are the
+    calibration of FETCH_SIZE / WRITE_SIZE); returns the measured copy rate in
+    GB/s (read + write bytes over the median HIP-event time), or None."""
     import torch
-    if args.copy_mib > 0:
-        a = torch.empty(args.copy_mib << 18, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
+    if args.copy_mib <= 0:
+        return None
+    a = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         b.copy_(a)
+        e1.record()
         torch.cuda.synchronize()
-        del a, b
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * (args.copy_mib << 20) / (float(np.median(ms)) * 1e-3) / 1e9
+
+
+def host_cpu():
+    """Model string and usable core count of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def _median_ms(fn, reps=5):
@@ -425,7 +488,7 @@ def main():
     log(f"plan: {info.n_inst} instances, {info.n_valid} valid, classes "
         f"{[(c.fp64, c.w, c.n, c.degree, c.parts) for c in cls]}, chunks {info.n_chunks}")
 
-    copy_calibration(args, dev)
+    copy_gbs = copy_calibration(args, dev)
 
     log("timing fp32")
     el, st = time_steps(plan, x32, stat, used, args.steps, args.warmup)
@@ -443,6 +506,8 @@ def main():
                    "spreaders": sorted({METHOD_NAME[c.method] for c in cls}), "kernel_width": cls[0].w,
                    "grid": cls[0].n, "degree": cls[0].degree, "parallelism": "single_gpu"},
         "all_instance_rate": info.n_inst * args.steps / el,
+        "copy_gbs": copy_gbs,
+        "host_cpu": host_cpu(),
     }
     stage_ms = {k: v[0] / args.steps for k, v in st.items()}
     out["stage_ms_per_step"] = stage_ms
@@ -475,7 +540,10 @@ def main():
         roof = {"kernel": kname, "bound": "alu", "achieved": achieved,
                 "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                 "traffic": committed_traffic(kname) if len(cls) == 1 else None,
-                "traffic_unit": "bytes per launch", "ops_per_point": ops / pts}
+                "traffic_unit": "bytes per launch", "ops_per_point": ops / pts,
+                "achieved_basis": "algorithmic VALU lane-operations of the per-sample op model "
+                                  "(algorithmic_ops) over the HIP-event launch time; peak = 256 CU x 64 lanes x "
+                                  "2.4 GHz, one FP32 or FP64 FMA per lane per cycle"}
     else:
         bytes_step = info.n_valid * n * 8 + info.stat_bins * 8
         achieved = bytes_step / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9
@@ -488,6 +556,7 @@ def main():
     # FFT/epilogue kernels over their summed time
     sf_bytes = (pts * 8 if args.method == "staged" else 0) + 2 * info.n_valid * n * 8 + info.stat_bins * 8
     out["spread_fft_hbm_gbs"] = sf_bytes / ((stage_ms["spread"] + stage_ms["epilogue"]) * 1e-3) / 1e9
+    out["spread_fft_hbm_frac"] = out["spread_fft_hbm_gbs"] / HBM_PEAK_GBS
 
     # accuracy: FP32 vs the FP64 path on every instance
     if not args.no_check:
@@ -584,6 +653,16 @@ def main():
             errs.append(np.linalg.norm(g - r) / np.linalg.norm(r))
         out["oracle_check"] = {"instances": len(idx), "spectra_rel_l2_max": float(np.max(errs))}
     plan.close()
+
+    # the paper's own beta-bank workload and the ragged batch, timed the same way
+    if not args.no_extra:
+        for name in ("paper_beta_bank", "ragged_512"):
+            r = measure_workload(args, dev, name, max(5, args.steps), check=4)
+            out[name] = {k: r[k] for k in ("value", "ms_per_step", "samples_per_s", "spread_ms_per_step",
+                                           "spread_valu_frac", "oracle_check") if k in r}
+            out[name]["workload"] = r["config"]["workload"]
+            out[name]["unit"] = "spectra/s"
+            out[name]["instances"] = r["config"]["instances"]
     print(json.dumps(out), flush=True)
 
 
