@@ -221,6 +221,35 @@ def measure_workload(args, dev, workload, steps, check=16, tune=False, method="a
     return out
 
 
+def mlp_step_timing(dev, B=1024, steps=200):
+    """One training step of the proposal's network (forward, backward, Adam) on a
+    batch of B rows: HIP-event time per step and the dense-product throughput of
+    its two hidden layers (forward, da1 and the two weight gradients)."""
+    import torch
+
+    import synth
+    from paper_2609_12476_amd.mlp import Mlp
+    g = torch.Generator(device=dev).manual_seed(5)
+    x = torch.randn(B, 64, generator=g, device=dev)
+    y = (torch.rand(B, generator=g, device=dev) < 0.5).float()
+    net = Mlp(max_batch=B, params=synth.mlp_init_params(5))
+    for _ in range(10):
+        net.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        net.train_step(x, y, 1e-3)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / steps * 1e3
+    net.close()
+    # dense flops per step: forward 2B(64*256 + 256*256), da1 2B*256*256, dW1 2B*64*256, dW2 2B*256*256
+    flops = 2.0 * B * (64 * 256 + 256 * 256) + 2.0 * B * 256 * 256 + 2.0 * B * (64 * 256 + 256 * 256)
+    return {"batch": B, "us_per_step": us, "dense_tflops": flops / (us * 1e-6) / 1e12,
+            "peak_fp32_mfma_tflops": 157.3}
+
+
 def other_workload(args, dev):
     """Throughput of the non-headline workloads (one JSON line each)."""
     steps = max(2, args.steps // (10 if args.workload == "full_sweep_6h" else 1))
@@ -663,6 +692,7 @@ def main():
             out[name]["workload"] = r["config"]["workload"]
             out[name]["unit"] = "spectra/s"
             out[name]["instances"] = r["config"]["instances"]
+        out["mlp_train_step"] = mlp_step_timing(dev)
     print(json.dumps(out), flush=True)
 
 

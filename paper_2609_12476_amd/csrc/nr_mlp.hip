@@ -4,6 +4,7 @@
 // region feature builder.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -78,6 +79,8 @@ __device__ __forceinline__ void rows_times_weights(const float* __restrict__ src
 {
     const int l = threadIdx.x & 63;
     const int m = l & 31, h = l >> 5;
+    // unrolled so that the weight loads of several steps are in flight together
+#pragma unroll 16
     for (int k = 0; k < KW; k += 2) {
         const float a = src[m * STRIDE + k + h];
         const float b0 = from_bf16(wt[(k + h) * HID + n0 + m]);
@@ -187,6 +190,7 @@ __global__ __launch_bounds__(BLK) void backward_act_kernel(
     }
     __syncthreads();
     const float wj = from_bf16(w3[j]);
+#pragma unroll 8
     for (int r = 0; r < RB; ++r) {
         float d = 0.0f;
         if (r < nr && h2[(r0 + r) * HID + j] > 0.0f) d = dzs[r] * wj;
@@ -216,34 +220,100 @@ __global__ __launch_bounds__(BLK) void backward_act_kernel(
     }
 }
 
-// One thread per parameter; sums over the batch rows in row order, in FP64.
-__global__ void weight_grad_kernel(const float* __restrict__ x, const float* __restrict__ h1,
-                                   const float* __restrict__ h2, const float* __restrict__ dz,
-                                   const float* __restrict__ da1, const float* __restrict__ da2,
-                                   int64_t B, float* __restrict__ grad)
+// Weight gradients as dense products on the matrix cores:
+//   dW1[j][k] = sum_r da1[r][j] x[r][k],   dW2[j][k] = sum_r da2[r][j] h1[r][k],
+// i.e. C = A B with A[j][r] = da[r][j] and B[r][k] = x[r][k] (or h1): the
+// batch row r is the contraction index.  The batch is cut into S chunks of
+// RC rows; wave (strip, chunk) accumulates a 32 x 64 strip of one matrix over
+// its chunk with v_mfma_f32_32x32x2f32 (FP32 operands, so the gradient keeps
+// FP32 precision) and stores it in the chunk's partial gradient.  Lane
+// (m, h) of a step over rows r, r + 1 supplies A[m][h] = da[r + h][j0 + m]
+// and B[h][n = m] = src[r + h][k0 + m] (each a pair of coalesced 32-float
+// row pieces); accumulator e of the lane is C[8 (e / 4) + 4 h + e % 4][m].
+// The bias and output-vector gradients (db1, db2, dw3, db3) are VALU sums
+// over the chunk by the remaining waves, one entry per lane.  A second pass
+// adds the S partials of every parameter in chunk order in FP64, so the
+// gradient is bitwise reproducible.
+constexpr int kW1Strips = HID / 32;                    // 32 x 64 strips of dW1 (64 columns)
+constexpr int kW2Strips = (HID / 32) * (HID / 64);     // of dW2
+constexpr int kVecStrips = 3 * (HID / 64) + 1;         // db1, db2, dw3 by 64 entries; db3
+constexpr int kGradStrips = kW1Strips + kW2Strips + kVecStrips;
+constexpr int kMaxChunks = 64;
+
+__host__ __device__ inline int grad_chunk_rows(int64_t B)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= NP) return;
-    double s = 0.0;
-    if (i < OFF_B1) {
-        const int j = i / IN, k = i % IN;
-        for (int64_t r = 0; r < B; ++r) s += (double)da1[r * HID + j] * (double)x[r * IN + k];
-    } else if (i < OFF_W2) {
-        const int j = i - OFF_B1;
-        for (int64_t r = 0; r < B; ++r) s += (double)da1[r * HID + j];
-    } else if (i < OFF_B2) {
-        const int q = i - OFF_W2, j = q / HID, k = q % HID;
-        for (int64_t r = 0; r < B; ++r) s += (double)da2[r * HID + j] * (double)h1[r * HID + k];
-    } else if (i < OFF_W3) {
-        const int j = i - OFF_B2;
-        for (int64_t r = 0; r < B; ++r) s += (double)da2[r * HID + j];
-    } else if (i < OFF_B3) {
-        const int j = i - OFF_W3;
-        for (int64_t r = 0; r < B; ++r) s += (double)dz[r] * (double)h2[r * HID + j];
-    } else {
-        for (int64_t r = 0; r < B; ++r) s += (double)dz[r];
+    // at least 32 rows per chunk, at most kMaxChunks chunks; even (MFMA steps of two rows)
+    int64_t rc = (B + kMaxChunks - 1) / kMaxChunks;
+    if (rc < 32) rc = 32;
+    return (int)((rc + 1) & ~int64_t(1));
+}
+
+__global__ __launch_bounds__(BLK) void weight_grad_partial_kernel(
+    const float* __restrict__ x, const float* __restrict__ h1, const float* __restrict__ h2,
+    const float* __restrict__ dz, const float* __restrict__ da1, const float* __restrict__ da2, int64_t B,
+    int rc, int n_chunks, float* __restrict__ part)
+{
+    const int wv = (int)(blockIdx.x * (BLK / 64) + (threadIdx.x >> 6));
+    if (wv >= kGradStrips * n_chunks) return;  // whole waves
+    const int strip = wv % kGradStrips, chunk = wv / kGradStrips;
+    const int l = threadIdx.x & 63;
+    const int m = l & 31, h = l >> 5;
+    const int64_t r0 = (int64_t)chunk * rc;
+    const int64_t r1 = (r0 + rc < B) ? r0 + rc : B;
+    float* out = part + (int64_t)chunk * NP;
+    if (strip < kW1Strips + kW2Strips) {
+        const float* A;
+        const float* S;
+        int ld, j0, k0, off, ldw;
+        if (strip < kW1Strips) {
+            A = da1; S = x; ld = IN; j0 = 32 * strip; k0 = 0; off = OFF_W1; ldw = IN;
+        } else {
+            const int q = strip - kW1Strips;
+            A = da2; S = h1; ld = HID; j0 = 32 * (q / (HID / 64)); k0 = 64 * (q % (HID / 64)); off = OFF_W2;
+            ldw = HID;
+        }
+        floatx16 c0, c1;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            c0[e] = 0.0f;
+            c1[e] = 0.0f;
+        }
+#pragma unroll 8
+        for (int64_t r = r0; r < r1; r += 2) {
+            const int64_t rr = r + h;
+            const bool in = rr < r1;
+            const float a = in ? A[rr * HID + j0 + m] : 0.0f;
+            const float b0 = in ? S[rr * ld + k0 + m] : 0.0f;
+            const float b1 = in ? S[rr * ld + k0 + 32 + m] : 0.0f;
+            c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, c1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int j = j0 + tile_row(e, h);
+            out[off + j * ldw + k0 + m] = c0[e];
+            out[off + j * ldw + k0 + 32 + m] = c1[e];
+        }
+        return;
     }
-    grad[i] = (float)s;
+    // vector gradients: one entry per lane
+    const int v = strip - kW1Strips - kW2Strips;
+    const int which = v / (HID / 64);          // 0 db1, 1 db2, 2 dw3, 3 db3
+    const int j = (v % (HID / 64)) * 64 + l;
+    float s = 0.0f;
+    if (which == 0) {
+        for (int64_t r = r0; r < r1; ++r) s += da1[r * HID + j];
+        out[OFF_B1 + j] = s;
+    } else if (which == 1) {
+        for (int64_t r = r0; r < r1; ++r) s += da2[r * HID + j];
+        out[OFF_B2 + j] = s;
+    } else if (which == 2) {
+        for (int64_t r = r0; r < r1; ++r) s = fmaf(dz[r], h2[r * HID + j], s);
+        out[OFF_W3 + j] = s;
+    } else if (l == 0) {
+        for (int64_t r = r0; r < r1; ++r) s += dz[r];
+        out[OFF_B3] = s;
+    }
 }
 
 // Mean of softplus(z) - y z over the batch, one workgroup, fixed order.
@@ -267,17 +337,55 @@ __global__ __launch_bounds__(BLK) void loss_kernel(const float* __restrict__ z,
     if (threadIdx.x == 0) *loss = (float)(part[0] / (double)B);
 }
 
-__global__ void adam_kernel(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                            const float* __restrict__ g, float lr, float c1, float c2)
+// The bfloat16 copies of parameter i (new value q) where the products read
+// them (see refresh_bf16_kernel); biases have none.
+__device__ __forceinline__ void store_bf16(int i, float q, bf16_t* __restrict__ w1t, bf16_t* __restrict__ w2,
+                                           bf16_t* __restrict__ w2t, bf16_t* __restrict__ w3)
+{
+    if (i < OFF_B1) {
+        w1t[(i % IN) * HID + i / IN] = to_bf16(q);
+    } else if (i >= OFF_W2 && i < OFF_B2) {
+        const int q2 = i - OFF_W2;
+        const bf16_t h = to_bf16(q);
+        w2[q2] = h;
+        w2t[(q2 % HID) * HID + q2 / HID] = h;
+    } else if (i >= OFF_W3 && i < OFF_B3) {
+        w3[i - OFF_W3] = to_bf16(q);
+    }
+}
+
+// One thread per parameter.  FROM_PARTS: the gradient is the sum over the
+// chunks, in chunk order, of the partial gradients (FP64; else it is read
+// from grad_in).  It is stored to grad_out when given.  ADAM: one Adam update
+// (beta1 0.9, beta2 0.999, eps 1e-8; c1, c2 the bias corrections) of the
+// masters and moments, and the bfloat16 copies of the new masters.
+template <bool FROM_PARTS, bool ADAM>
+__global__ void update_kernel(const float* __restrict__ part, int n_chunks, const float* __restrict__ grad_in,
+                              float* __restrict__ grad_out, float* __restrict__ p, float* __restrict__ m,
+                              float* __restrict__ v, float lr, float c1, float c2, bf16_t* __restrict__ w1t,
+                              bf16_t* __restrict__ w2, bf16_t* __restrict__ w2t, bf16_t* __restrict__ w3)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= NP) return;
-    const float gi = g[i];
-    const float mi = 0.9f * m[i] + 0.1f * gi;
-    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    float gi;
+    if (FROM_PARTS) {
+        double s = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < n_chunks; ++c) s += (double)part[(int64_t)c * NP + i];
+        gi = (float)s;
+    } else {
+        gi = grad_in[i];
+    }
+    if (grad_out) grad_out[i] = gi;
+    if (ADAM) {
+        const float mi = 0.9f * m[i] + 0.1f * gi;
+        const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float q = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+        p[i] = q;
+        store_bf16(i, q, w1t, w2, w2t, w3);
+    }
 }
 
 // ------------------------------------------------------------- features --
@@ -329,11 +437,13 @@ struct nr_mlp_s {
     bf16_t *w1t = nullptr, *w2 = nullptr, *w2t = nullptr, *w3 = nullptr;
     float *h1 = nullptr, *h2 = nullptr, *z = nullptr, *dz = nullptr, *da1 = nullptr, *da2 = nullptr;
     float* loss = nullptr;
+    float* gpart = nullptr;   // per-chunk partial gradients [gchunks][NP]
+    int gchunks = 0;
     ~nr_mlp_s()
     {
         for (void* q : {(void*)p, (void*)m, (void*)v, (void*)grad, (void*)w1t, (void*)w2, (void*)w2t,
                         (void*)w3, (void*)h1, (void*)h2, (void*)z, (void*)dz, (void*)da1, (void*)da2,
-                        (void*)loss})
+                        (void*)loss, (void*)gpart})
             if (q) (void)hipFree(q);
     }
 };
@@ -385,7 +495,17 @@ nr_status run_forward(nr_mlp m, const float* x, int64_t B, bool keep, float* log
     return hip_status(m, hipGetLastError(), "forward");
 }
 
-nr_status run_gradient(nr_mlp m, const float* x, const float* y, int64_t B, float* grad, float* loss)
+// Bias corrections of the next Adam step (advances the step count).
+void adam_corrections(nr_mlp m, float* c1, float* c2)
+{
+    m->step += 1;
+    *c1 = (float)(1.0 - std::pow(0.9, (double)m->step));
+    *c2 = (float)(1.0 - std::pow(0.999, (double)m->step));
+}
+
+// Gradient of the batch into grad (or NULL); lr > 0: followed by one Adam
+// update in the same pass over the parameters.
+nr_status run_gradient(nr_mlp m, const float* x, const float* y, int64_t B, float* grad, float* loss, float lr)
 {
     nr_status st = run_forward(m, x, B, true, m->z);
     if (st != NR_OK) return st;
@@ -393,24 +513,41 @@ nr_status run_gradient(nr_mlp m, const float* x, const float* y, int64_t B, floa
     backward_act_kernel<<<blocks, BLK, 0, m->stream>>>(m->z, y, B, m->h1, m->h2, m->w2, m->w3, m->dz, m->da2,
                                                        m->da1);
     if ((st = hip_status(m, hipGetLastError(), "backward")) != NR_OK) return st;
-    weight_grad_kernel<<<(NP + 255) / 256, 256, 0, m->stream>>>(x, m->h1, m->h2, m->dz, m->da1, m->da2, B, grad);
+    const int rc = grad_chunk_rows(B);
+    const int n_chunks = (int)((B + rc - 1) / rc);
+    if (n_chunks > m->gchunks) {
+        set_err(m, "internal: gradient chunks exceed the workspace");
+        return NR_ERR_DEVICE;
+    }
+    const unsigned gblocks = (unsigned)((kGradStrips * n_chunks + BLK / 64 - 1) / (BLK / 64));
+    weight_grad_partial_kernel<<<gblocks, BLK, 0, m->stream>>>(x, m->h1, m->h2, m->dz, m->da1, m->da2, B, rc,
+                                                               n_chunks, m->gpart);
     if ((st = hip_status(m, hipGetLastError(), "weight gradients")) != NR_OK) return st;
     if (loss) {
         loss_kernel<<<1, BLK, 0, m->stream>>>(m->z, y, B, loss);
         if ((st = hip_status(m, hipGetLastError(), "loss")) != NR_OK) return st;
     }
-    return NR_OK;
+    const unsigned ublocks = (NP + 255) / 256;
+    if (lr > 0.0f) {
+        float c1, c2;
+        adam_corrections(m, &c1, &c2);
+        update_kernel<true, true><<<ublocks, 256, 0, m->stream>>>(m->gpart, n_chunks, nullptr, grad, m->p, m->m,
+                                                                  m->v, lr, c1, c2, m->w1t, m->w2, m->w2t, m->w3);
+    } else {
+        update_kernel<true, false><<<ublocks, 256, 0, m->stream>>>(m->gpart, n_chunks, nullptr, grad, nullptr,
+                                                                   nullptr, nullptr, 0.0f, 1.0f, 1.0f, nullptr,
+                                                                   nullptr, nullptr, nullptr);
+    }
+    return hip_status(m, hipGetLastError(), "gradient sum / Adam");
 }
 
 nr_status run_adam(nr_mlp m, const float* grad, float lr)
 {
-    m->step += 1;
-    const float c1 = (float)(1.0 - std::pow(0.9, (double)m->step));
-    const float c2 = (float)(1.0 - std::pow(0.999, (double)m->step));
-    adam_kernel<<<(NP + 255) / 256, 256, 0, m->stream>>>(m->p, m->m, m->v, grad, lr, c1, c2);
-    nr_status st = hip_status(m, hipGetLastError(), "adam");
-    if (st != NR_OK) return st;
-    return refresh(m);
+    float c1, c2;
+    adam_corrections(m, &c1, &c2);
+    update_kernel<false, true><<<(NP + 255) / 256, 256, 0, m->stream>>>(nullptr, 0, grad, nullptr, m->p, m->m, m->v,
+                                                                        lr, c1, c2, m->w1t, m->w2, m->w2t, m->w3);
+    return hip_status(m, hipGetLastError(), "adam");
 }
 
 }  // namespace
@@ -452,6 +589,9 @@ nr_status nr_mlp_create(nr_mlp* out, int64_t max_batch, void* stream)
     if (e == hipSuccess) e = dalloc(&m->z, (size_t)max_batch);
     if (e == hipSuccess) e = dalloc(&m->dz, (size_t)max_batch);
     if (e == hipSuccess) e = dalloc(&m->loss, 1);
+    // chunks of any batch B <= max_batch: at most min(kMaxChunks, ceil(B / 32))
+    m->gchunks = (int)std::min<int64_t>(kMaxChunks, (max_batch + 31) / 32);
+    if (e == hipSuccess) e = dalloc(&m->gpart, (size_t)m->gchunks * NP);
     if (e == hipSuccess) e = hipMemsetAsync(m->p, 0, NP * sizeof(float), m->stream);
     if (e == hipSuccess) e = hipMemsetAsync(m->m, 0, NP * sizeof(float), m->stream);
     if (e == hipSuccess) e = hipMemsetAsync(m->v, 0, NP * sizeof(float), m->stream);
@@ -534,7 +674,7 @@ nr_status nr_mlp_gradient(nr_mlp m, const float* x, const float* y, int64_t B, f
     if (!m || !x || !y) return NR_ERR_INVALID_ARG;
     nr_status st = check_batch(m, B);
     if (st != NR_OK) return st;
-    st = run_gradient(m, x, y, B, m->grad, loss);
+    st = run_gradient(m, x, y, B, m->grad, loss, 0.0f);
     if (st == NR_OK && grad)
         st = hip_status(m, hipMemcpyAsync(grad, m->grad, NP * sizeof(float), hipMemcpyDeviceToDevice, m->stream),
                         "gradient copy");
@@ -552,9 +692,7 @@ nr_status nr_mlp_train_step(nr_mlp m, const float* x, const float* y, int64_t B,
     if (!m || !x || !y || !(lr > 0.0f)) return NR_ERR_INVALID_ARG;
     nr_status st = check_batch(m, B);
     if (st != NR_OK) return st;
-    st = run_gradient(m, x, y, B, m->grad, loss);
-    if (st != NR_OK) return st;
-    return run_adam(m, m->grad, lr);
+    return run_gradient(m, x, y, B, nullptr, loss, lr);
 }
 
 nr_status nr_mlp_region_features(const float* stat, const int32_t* n_used, int32_t n_mc, int32_t n_sub,
