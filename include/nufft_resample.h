@@ -160,7 +160,13 @@ typedef struct {
                                    power of two); 0: chosen from the sample density */
     int32_t moment_mode;        /* spreader moments: 0 automatic, 1 restarted per grid cell,
                                    2 cumulative with snapshots (FP32 classes, degree <= 12) */
-    int32_t reserved2;
+    int32_t epilogue;           /* 2: classes of at most four waves per instance run the FFT,
+                                   deconvolution and power inside the spreader's workgroup (the
+                                   grid never leaves LDS; App. A's interpolate-FFT-deconvolve as
+                                   one kernel), unless the FFT's second buffer would cost the
+                                   spreader workgroups per compute unit; 1: always a separate
+                                   epilogue kernel reading the grids from memory; 0: as 2 in
+                                   plans that fill the GPU (16384 or more waves), else as 1 */
 } nr_options;
 
 typedef struct {
@@ -193,7 +199,7 @@ typedef struct {
     int32_t method;          /* NR_METHOD_STAGED, NR_METHOD_FUSED or NR_METHOD_CELLRUN */
     int32_t flush_period;    /* spreader steps between collective flushes */
     int32_t snap;            /* 1: cumulative spreader moments with snapshots; 0: per cell */
-    int32_t reserved;
+    int32_t epi_fused;       /* 1: the spreader runs the FFT / deconvolution / power */
     int64_t series_terms;    /* sum over instances of L x (degree of the tau series) */
     int64_t fallback_points; /* samples of instances using the log1p/expm1 form of tau */
 } nr_class_info;

@@ -56,12 +56,12 @@ struct SegDev {
     int32_t pad_;
 };
 
+
 struct FftPlanDev {
     int32_t n;
     int32_t nr;              // number of passes
     int32_t radix[kMaxRadix];
 };
-
 // Arguments of the tau and spreading kernels for one chunk of one class.
 struct SpreadArgs {
     const InstDev* inst;     // class instances
@@ -80,6 +80,15 @@ struct SpreadArgs {
     int32_t flush_period;    // steps between collective flushes (power of two)
     int32_t strain_complex;
     int32_t snap;            // 1: cumulative moments with snapshots; 0: per-cell moments
+    // fused epilogue (epi_fused = 1): the spreader itself runs the FFT of each
+    // instance's grid in LDS, deconvolves and writes the outputs of the call
+    // (EpilogueOut::mode); the grid never leaves LDS
+    int32_t epi_fused;
+    int32_t kmax;            // largest K of the class (power-row stride)
+    int64_t row_base;        // first element of the class's power rows
+    const void* dec;         // [n] real deconvolution factors indexed by mode mod n
+    const void* twiddle;     // [n] complex exp(-2 pi i t / n)
+    FftPlanDev fft;
 };
 
 // Workgroups of one launch of a class chunk, and grid slots per instance:
@@ -121,6 +130,9 @@ struct EpilogueOut {
     void* stat;
     int32_t* n_used;
     void* rows;              // power rows of the two-pass segment sum (first pass output)
+    int32_t mode;            // spreaders of fused classes: 0 write the grid (a separate epilogue
+                             // follows), 1 power rows, 2 spectra and/or power at the bin offsets
+    int32_t out_fp64;        // outputs and rows are double (else float)
 };
 
 // Launch wrappers (defined in nr_kernels.hip).
@@ -138,7 +150,7 @@ struct SpreadTable {
     int32_t ncls;
 };
 hipError_t launch_spread_multi(const SpreadTable& t, int64_t blocks, int fp64, int deg, int fused, int cplx,
-                               int snap, size_t lds, hipStream_t st);
+                               int snap, size_t lds, const EpilogueOut& out, hipStream_t st);
 // The same for the epilogue: block_off[m][c] is the first workgroup of class
 // c in mode m (0 spectra or power rows, 1 segment sum or row sums).
 struct EpilogueTable {
@@ -155,7 +167,8 @@ hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st);
 hipError_t launch_direct(const SpreadArgs& a, const EpilogueArgs& e, const EpilogueOut& o, int mode, int fp64,
                          int out_fp64, hipStream_t st);
 // fused: 0 staged (reads the point stream), 1 fused sample runs, 2 fused cell runs.
-hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st);
+hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, const EpilogueOut& out,
+                         hipStream_t st);
 hipError_t launch_epilogue_spectra(const EpilogueArgs& a, const EpilogueOut& out, int fp64,
                                    int out_fp64, hipStream_t st);
 // Second pass of the two-pass segment sum: stat += weighted sums of the
@@ -171,7 +184,10 @@ hipError_t launch_fill_invalid(const int32_t* inv_inst, const int64_t* bin_off,
                                int64_t n_inst, hipStream_t st);
 hipError_t launch_finite_scan(const void* strain, int64_t n, int fp64, int32_t* flag,
                               hipStream_t st);
-size_t spread_lds_bytes(int fp64, int n);
+// LDS of a spreader workgroup: phase table and one grid per wave; with
+// pong = 1 (fused epilogue, one wave per instance) a second grid per wave
+// holds the other half of the FFT's ping-pong.
+size_t spread_lds_bytes(int fp64, int n, int pong = 0);
 int phase_table_size(int fp64);
 constexpr int kHornerPad = 16;   // zero coefficients appended to every class's tau series
 size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode);

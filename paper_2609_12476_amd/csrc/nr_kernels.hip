@@ -243,6 +243,143 @@ __global__ __launch_bounds__(kBlock) void tau_kernel(SpreadArgs a)
     }
 }
 
+// ------------------------------------------------------------------ FFT --
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
+{
+    return cpx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b)
+{
+    return cpx<T>{a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b)
+{
+    return cpx<T>{a.x - b.x, a.y - b.y};
+}
+// -i z
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a)
+{
+    return cpx<T>{a.y, -a.x};
+}
+
+// In-register DFT of length R (forward sign): y_q = sum_r v_r exp(-2 pi i r q / R).
+template <typename T>
+__device__ __forceinline__ void dft_small(cpx<T>* v, int R)
+{
+    if (R == 2) {
+        const cpx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if (R == 3) {
+        const T s3 = T(0.86602540378443864676);
+        const cpx<T> t = cadd(v[1], v[2]);
+        const cpx<T> d = csub(v[1], v[2]);
+        const cpx<T> m = cpx<T>{v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+        const cpx<T> r = cpx<T>{s3 * d.y, -s3 * d.x};  // -i s3 d
+        v[0] = cadd(v[0], t);
+        v[1] = cadd(m, r);
+        v[2] = csub(m, r);
+    } else if (R == 4) {
+        const cpx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        const cpx<T> c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, mul_mi(d));
+        v[3] = csub(b, mul_mi(d));
+    } else {  // R == 5
+        const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+        const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+        const cpx<T> t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
+        const cpx<T> t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
+        const cpx<T> a1 = cpx<T>{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+        const cpx<T> a2 = cpx<T>{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+        const cpx<T> b1 = cpx<T>{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y};
+        const cpx<T> b2 = cpx<T>{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y};
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, mul_mi(b1));
+        v[4] = csub(a1, mul_mi(b1));
+        v[2] = cadd(a2, mul_mi(b2));
+        v[3] = csub(a2, mul_mi(b2));
+    }
+}
+
+// Lanes cooperating on one transform: 16 for grids up to 128 points (sixteen
+// transforms per workgroup), one wave up to 512, the whole workgroup above
+// (which keeps the LDS of the largest grids within one workgroup).
+__host__ __device__ __forceinline__ int team_size_for(int n) { return n <= 128 ? 16 : (n <= 512 ? kWave : kBlock); }
+
+// Synchronise the lanes of a team: teams inside one wave only need their LDS
+// writes completed (the wave runs in lockstep); larger teams use the
+// workgroup barrier.  Uniform across the workgroup.
+__device__ __forceinline__ void team_sync(int ts)
+{
+    if (ts > kWave) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+}
+
+// Stockham autosort FFT of the team's n points (ping-pong between buf[0..n)
+// and buf[n..2n)).  Pass with radix R and span Ns (product of the earlier
+// radices): butterfly j (0 <= j < n/R) takes inputs j + r n/R, applies the
+// twiddles exp(-2 pi i r k / (Ns R)) with k = j mod Ns, and writes output q
+// to (j / Ns) Ns R + k + q Ns.  tw is the LDS copy of exp(-2 pi i t / n).
+// Every lane of the workgroup runs every pass.  Returns the buffer holding
+// the result.
+// One pass of radix R (a compile-time constant, so the R values of a
+// butterfly stay in registers).
+template <typename T, int R>
+__device__ __forceinline__ void fft_pass(const cpx<T>* src, cpx<T>* dst, const cpx<T>* tw, int n, int Ns, int tid,
+                                         int ts)
+{
+    const int nb = n / R;
+    const int twstep = n / (Ns * R);
+    for (int j = tid; j < nb; j += ts) {
+        const int k = j % Ns;
+        cpx<T> v[R];
+        v[0] = src[j];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(src[j + r * nb], tw[r * k * twstep]);
+        dft_small(v, R);
+        const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
+    }
+}
+
+template <typename T>
+__device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* tw, const FftPlanDev& fp, int tid, int ts)
+{
+    const int n = fp.n;
+    cpx<T>* src = buf;
+    cpx<T>* dst = buf + n;
+    int Ns = 1;
+    const int nr = fp.nr;
+    for (int p = 0; p < nr; ++p) {
+        const int R = fp.radix[p];
+        switch (R) {
+        case 2: fft_pass<T, 2>(src, dst, tw, n, Ns, tid, ts); break;
+        case 3: fft_pass<T, 3>(src, dst, tw, n, Ns, tid, ts); break;
+        case 4: fft_pass<T, 4>(src, dst, tw, n, Ns, tid, ts); break;
+        default: fft_pass<T, 5>(src, dst, tw, n, Ns, tid, ts); break;
+        }
+        team_sync(ts);
+        cpx<T>* t = src;
+        src = dst;
+        dst = t;
+        Ns *= R;
+    }
+    return src;
+}
+
 // --------------------------------------------------------------- spread --
 
 // exp(2 pi i k / N) for k < N, the coarse part of the heterodyne phasor.
@@ -416,6 +553,87 @@ __device__ __forceinline__ void flush_diff(const Moments<T, D>& E, const Moments
     flush<T, D>(V, g, A, grid, n, w);
 }
 
+// Grid stride of a spreader workgroup's per-wave grids: a second grid per
+// wave when the fused epilogue runs an instance's FFT within one wave.
+__device__ __forceinline__ int grid_stride(const SpreadArgs& a, int wpi) { return (a.epi_fused && wpi == 1) ? 2 * a.n : a.n; }
+
+// After spreading, the instance's grids (one per wave of the instance, at
+// lds + (first_wave + q) gstride) become either its partial grid in global
+// memory (call mode 0, or a class without the fused epilogue: a separate
+// epilogue kernel follows) or, fused, are summed into the first wave's grid,
+// transformed in LDS by the instance's waves (the grid after it is the
+// Stockham ping-pong half: the next wave's grid, or the wave's own second
+// grid), deconvolved and written as power rows (mode 1) or spectra / power
+// (mode 2), with the arithmetic of the separate epilogue.
+// Every wave of the workgroup takes part (the transforms synchronise);
+// waves past the last instance transform their zero grids and write nothing.
+template <typename T>
+__device__ __forceinline__ void finish_instance(const SpreadArgs& a, const EpilogueOut& o, int64_t item, int slot,
+                                                cpx<T>* lds, int wave, int lane, int wpi)
+{
+    const int n = a.n;
+    const int gs = grid_stride(a, wpi);
+    const int first_wave = (wave / wpi) * wpi;
+    const bool live = item < a.count;
+    if (!a.epi_fused || o.mode == 0) {
+        if (!live) return;
+        // Sum the grids of the instance's waves in this workgroup in wave
+        // order and store them as the workgroup's partial grid (slot).
+        cpx<T>* out = reinterpret_cast<cpx<T>*>(a.grid) + (item * grid_slots(a.parts) + slot) * n;
+        for (int c = (wave % wpi) * kWave + lane; c < n; c += kWave * wpi) {
+            T r = T(0), i = T(0);
+            for (int q = 0; q < wpi; ++q) {
+                const cpx<T> gv = lds[(first_wave + q) * gs + c];
+                r += gv.x;
+                i += gv.y;
+            }
+            out[c] = cpx<T>{r, i};
+        }
+        return;
+    }
+    cpx<T>* buf = lds + first_wave * gs;
+    const int ts = wpi * kWave, tid = (wave % wpi) * kWave + lane;
+    if (wpi > 1) {
+        for (int c = tid; c < n; c += ts) {
+            T r = T(0), i = T(0);
+            for (int q = 0; q < wpi; ++q) {
+                const cpx<T> gv = lds[(first_wave + q) * gs + c];
+                r += gv.x;
+                i += gv.y;
+            }
+            buf[c] = cpx<T>{r, i};
+        }
+    }
+    __syncthreads();
+    const cpx<T>* res = fft_team<T>(buf, reinterpret_cast<const cpx<T>*>(a.twiddle), a.fft, tid, ts);
+    if (!live) return;
+    const InstDev d = a.inst[a.first + item];
+    const T* __restrict__ dec = reinterpret_cast<const T*>(a.dec);
+    for (int k = tid; k < d.K; k += ts) {
+        int l = k - d.m0;
+        if (l < 0) l += n;
+        const T f = dec[l];
+        const cpx<T> X = cpx<T>{res[l].x * f, res[l].y * f};
+        if (o.out_fp64) {
+            const double pw = (double)X.x * (double)X.x + (double)X.y * (double)X.y;
+            if (o.mode == 1) {
+                reinterpret_cast<double*>(o.rows)[a.row_base + (int64_t)d.entry * a.kmax + k] = pw;
+            } else {
+                if (o.spectra) reinterpret_cast<cpx<double>*>(o.spectra)[d.bin_off + k] = cpx<double>{(double)X.x, (double)X.y};
+                if (o.power) reinterpret_cast<double*>(o.power)[d.bin_off + k] = pw;
+            }
+        } else {
+            const float pw = (float)X.x * (float)X.x + (float)X.y * (float)X.y;
+            if (o.mode == 1) {
+                reinterpret_cast<float*>(o.rows)[a.row_base + (int64_t)d.entry * a.kmax + k] = pw;
+            } else {
+                if (o.spectra) reinterpret_cast<cpx<float>*>(o.spectra)[d.bin_off + k] = cpx<float>{(float)X.x, (float)X.y};
+                if (o.power) reinterpret_cast<float*>(o.power)[d.bin_off + k] = pw;
+            }
+        }
+    }
+}
+
 // One wave per (instance, part).  Each lane walks its run of samples in
 // order; because tau is monotone in t the support's first cell g only
 // moves forward (and wraps once per period), so a lane keeps the Chebyshev
@@ -431,7 +649,7 @@ __device__ __forceinline__ void flush_diff(const Moments<T, D>& E, const Moments
 // Each wave owns its grid copy, so the LDS additions of one grid come from
 // one wave in program order and the result does not depend on scheduling.
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-__device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock)
+__device__ __forceinline__ void spread_block(const SpreadArgs& a, const EpilogueOut& o, int64_t lblock)
 {
     using P = typename PointOf<T>::type;
     constexpr int NT = 1 << PhaseTable<T>::bits;
@@ -443,14 +661,15 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock
     const int lane = threadIdx.x & 63;
     const int parts = a.parts;
     const int n = a.n, w = a.w;
-    cpx<T>* grid = lds + wave * n;
+    // waves of one instance inside this workgroup
+    const int wpi = parts < 4 ? parts : 4;
+    cpx<T>* grid = lds + wave * grid_stride(a, wpi);
     const cpx<T>* gtab = reinterpret_cast<const cpx<T>*>(a.phase_table);
     for (int k = threadIdx.x; k < NT; k += kBlock) tab[k] = gtab[k];
     for (int c = lane; c < n; c += kWave) grid[c] = cpx<T>{T(0), T(0)};
     __syncthreads();
 
-    // waves of one instance inside this workgroup, which instance, which part
-    const int wpi = parts < 4 ? parts : 4;
+    // which instance, which part
     int64_t item;
     int part, slot = 0;
     if (parts <= 4) {
@@ -546,28 +765,13 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, int64_t lblock
         }
     }
     __syncthreads();
-
-    if (item < a.count) {
-        // Sum the grids of the instance's waves in this workgroup in wave
-        // order and store them as the workgroup's partial grid (slot).
-        const int first_wave = (wave / wpi) * wpi;
-        cpx<T>* out = reinterpret_cast<cpx<T>*>(a.grid) + (item * grid_slots(parts) + slot) * n;
-        for (int c = (wave % wpi) * kWave + lane; c < n; c += kWave * wpi) {
-            T r = T(0), i = T(0);
-            for (int q = 0; q < wpi; ++q) {
-                const cpx<T> gv = lds[(first_wave + q) * n + c];
-                r += gv.x;
-                i += gv.y;
-            }
-            out[c] = cpx<T>{r, i};
-        }
-    }
+    finish_instance<T>(a, o, item, slot, lds, wave, lane, wpi);
 }
 
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-__global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a)
+__global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a, EpilogueOut o)
 {
-    spread_block<T, D, FUSED, CPLX, SNAP>(a, blockIdx.x);
+    spread_block<T, D, FUSED, CPLX, SNAP>(a, o, blockIdx.x);
 }
 
 // ------------------------------------------------- cell-run schedule --
@@ -642,7 +846,7 @@ __device__ __forceinline__ void cell_quad(const TauConsts& tc, double top, const
 }
 
 template <typename T, int D, bool CPLX>
-__device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t lblock)
+__device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, const EpilogueOut& o, int64_t lblock)
 {
     constexpr int NT = 1 << PhaseTable<T>::bits;
     using E = typename std::conditional<CPLX, cpx<T>, T>::type;
@@ -654,13 +858,13 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
     const int lane = threadIdx.x & 63;
     const int parts = a.parts;
     const int n = a.n, w = a.w;
-    cpx<T>* grid = lds + wave * n;
+    const int wpi = parts < 4 ? parts : 4;
+    cpx<T>* grid = lds + wave * grid_stride(a, wpi);
     const cpx<T>* gtab = reinterpret_cast<const cpx<T>*>(a.phase_table);
     for (int k = threadIdx.x; k < NT; k += kBlock) tab[k] = gtab[k];
     for (int c = lane; c < n; c += kWave) grid[c] = cpx<T>{T(0), T(0)};
     __syncthreads();
 
-    const int wpi = parts < 4 ? parts : 4;
     int64_t item;
     int part, slot = 0;
     if (parts <= 4) {
@@ -730,20 +934,7 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, int64_t l
         }
     }
     __syncthreads();
-
-    if (item < a.count) {
-        const int first_wave = (wave / wpi) * wpi;
-        cpx<T>* out = reinterpret_cast<cpx<T>*>(a.grid) + (item * grid_slots(parts) + slot) * n;
-        for (int c = (wave % wpi) * kWave + lane; c < n; c += kWave * wpi) {
-            T r = T(0), i = T(0);
-            for (int q = 0; q < wpi; ++q) {
-                const cpx<T> gv = lds[(first_wave + q) * n + c];
-                r += gv.x;
-                i += gv.y;
-            }
-            out[c] = cpx<T>{r, i};
-        }
-    }
+    finish_instance<T>(a, o, item, slot, lds, wave, lane, wpi);
 }
 
 // Occupancy of the cell-run kernel: six waves per SIMD (at most 80 VGPRs)
@@ -756,9 +947,9 @@ struct RunsWaves {
 
 template <typename T, int D, bool CPLX>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RunsWaves<T, D, CPLX>::value))) void
-spread_runs_kernel(SpreadArgs a)
+spread_runs_kernel(SpreadArgs a, EpilogueOut o)
 {
-    spread_runs_block<T, D, CPLX>(a, blockIdx.x);
+    spread_runs_block<T, D, CPLX>(a, o, blockIdx.x);
 }
 
 // Class of workgroup b of a multi-class launch (block_off is ascending).
@@ -770,155 +961,18 @@ __device__ __forceinline__ int class_of_block(const int64_t* __restrict__ block_
 }
 
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-__global__ __launch_bounds__(kBlock) void spread_multi_kernel(const SpreadTable t)
+__global__ __launch_bounds__(kBlock) void spread_multi_kernel(const SpreadTable t, EpilogueOut o)
 {
     const int c = class_of_block(t.block_off, t.ncls, blockIdx.x);
-    spread_block<T, D, FUSED, CPLX, SNAP>(t.a[c], (int64_t)blockIdx.x - t.block_off[c]);
+    spread_block<T, D, FUSED, CPLX, SNAP>(t.a[c], o, (int64_t)blockIdx.x - t.block_off[c]);
 }
 
 template <typename T, int D, bool CPLX>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RunsWaves<T, D, CPLX>::value))) void
-spread_runs_multi_kernel(const SpreadTable t)
+spread_runs_multi_kernel(const SpreadTable t, EpilogueOut o)
 {
     const int c = class_of_block(t.block_off, t.ncls, blockIdx.x);
-    spread_runs_block<T, D, CPLX>(t.a[c], (int64_t)blockIdx.x - t.block_off[c]);
-}
-
-// ------------------------------------------------------------------ FFT --
-
-template <typename T>
-__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b)
-{
-    return cpx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename T>
-__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b)
-{
-    return cpx<T>{a.x + b.x, a.y + b.y};
-}
-template <typename T>
-__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b)
-{
-    return cpx<T>{a.x - b.x, a.y - b.y};
-}
-// -i z
-template <typename T>
-__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a)
-{
-    return cpx<T>{a.y, -a.x};
-}
-
-// In-register DFT of length R (forward sign): y_q = sum_r v_r exp(-2 pi i r q / R).
-template <typename T>
-__device__ __forceinline__ void dft_small(cpx<T>* v, int R)
-{
-    if (R == 2) {
-        const cpx<T> a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
-    } else if (R == 3) {
-        const T s3 = T(0.86602540378443864676);
-        const cpx<T> t = cadd(v[1], v[2]);
-        const cpx<T> d = csub(v[1], v[2]);
-        const cpx<T> m = cpx<T>{v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
-        const cpx<T> r = cpx<T>{s3 * d.y, -s3 * d.x};  // -i s3 d
-        v[0] = cadd(v[0], t);
-        v[1] = cadd(m, r);
-        v[2] = csub(m, r);
-    } else if (R == 4) {
-        const cpx<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-        const cpx<T> c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
-        v[0] = cadd(a, c);
-        v[2] = csub(a, c);
-        v[1] = cadd(b, mul_mi(d));
-        v[3] = csub(b, mul_mi(d));
-    } else {  // R == 5
-        const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
-        const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
-        const cpx<T> t1 = cadd(v[1], v[4]), d1 = csub(v[1], v[4]);
-        const cpx<T> t2 = cadd(v[2], v[3]), d2 = csub(v[2], v[3]);
-        const cpx<T> a1 = cpx<T>{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
-        const cpx<T> a2 = cpx<T>{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
-        const cpx<T> b1 = cpx<T>{s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y};
-        const cpx<T> b2 = cpx<T>{s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y};
-        v[0] = cadd(v[0], cadd(t1, t2));
-        v[1] = cadd(a1, mul_mi(b1));
-        v[4] = csub(a1, mul_mi(b1));
-        v[2] = cadd(a2, mul_mi(b2));
-        v[3] = csub(a2, mul_mi(b2));
-    }
-}
-
-// Lanes cooperating on one transform: 16 for grids up to 128 points (sixteen
-// transforms per workgroup), one wave up to 512, the whole workgroup above
-// (which keeps the LDS of the largest grids within one workgroup).
-__host__ __device__ __forceinline__ int team_size_for(int n) { return n <= 128 ? 16 : (n <= 512 ? kWave : kBlock); }
-
-// Synchronise the lanes of a team: teams inside one wave only need their LDS
-// writes completed (the wave runs in lockstep); larger teams use the
-// workgroup barrier.  Uniform across the workgroup.
-__device__ __forceinline__ void team_sync(int ts)
-{
-    if (ts > kWave) {
-        __syncthreads();
-    } else {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
-}
-
-// Stockham autosort FFT of the team's n points (ping-pong between buf[0..n)
-// and buf[n..2n)).  Pass with radix R and span Ns (product of the earlier
-// radices): butterfly j (0 <= j < n/R) takes inputs j + r n/R, applies the
-// twiddles exp(-2 pi i r k / (Ns R)) with k = j mod Ns, and writes output q
-// to (j / Ns) Ns R + k + q Ns.  tw is the LDS copy of exp(-2 pi i t / n).
-// Every lane of the workgroup runs every pass.  Returns the buffer holding
-// the result.
-// One pass of radix R (a compile-time constant, so the R values of a
-// butterfly stay in registers).
-template <typename T, int R>
-__device__ __forceinline__ void fft_pass(const cpx<T>* src, cpx<T>* dst, const cpx<T>* tw, int n, int Ns, int tid,
-                                         int ts)
-{
-    const int nb = n / R;
-    const int twstep = n / (Ns * R);
-    for (int j = tid; j < nb; j += ts) {
-        const int k = j % Ns;
-        cpx<T> v[R];
-        v[0] = src[j];
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(src[j + r * nb], tw[r * k * twstep]);
-        dft_small(v, R);
-        const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-        for (int q = 0; q < R; ++q) dst[base + q * Ns] = v[q];
-    }
-}
-
-template <typename T>
-__device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* tw, const FftPlanDev& fp, int tid, int ts)
-{
-    const int n = fp.n;
-    cpx<T>* src = buf;
-    cpx<T>* dst = buf + n;
-    int Ns = 1;
-    const int nr = fp.nr;
-    for (int p = 0; p < nr; ++p) {
-        const int R = fp.radix[p];
-        switch (R) {
-        case 2: fft_pass<T, 2>(src, dst, tw, n, Ns, tid, ts); break;
-        case 3: fft_pass<T, 3>(src, dst, tw, n, Ns, tid, ts); break;
-        case 4: fft_pass<T, 4>(src, dst, tw, n, Ns, tid, ts); break;
-        default: fft_pass<T, 5>(src, dst, tw, n, Ns, tid, ts); break;
-        }
-        team_sync(ts);
-        cpx<T>* t = src;
-        src = dst;
-        dst = t;
-        Ns *= R;
-    }
-    return src;
+    spread_runs_block<T, D, CPLX>(t.a[c], o, (int64_t)blockIdx.x - t.block_off[c]);
 }
 
 // LDS layout of the epilogue kernels: twiddles [n], then per team 2n points,
@@ -1319,11 +1373,11 @@ static void allow_lds(K* kernel, size_t bytes)
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-size_t spread_lds_bytes(int fp64, int n)
+size_t spread_lds_bytes(int fp64, int n, int pong)
 {
     const size_t csize = fp64 ? 16 : 8;
     const size_t table = fp64 ? (size_t(1) << PhaseTable<double>::bits) : (size_t(1) << PhaseTable<float>::bits);
-    return (table + (size_t)4 * n) * csize;
+    return (table + (size_t)(pong ? 8 : 4) * n) * csize;
 }
 
 int phase_table_size(int fp64)
@@ -1386,42 +1440,43 @@ hipError_t launch_tau(const SpreadArgs& a, int fp64, hipStream_t st)
 }
 
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-static void launch_spread_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStream_t st)
+static void launch_spread_k(const SpreadArgs& a, const EpilogueOut& o, dim3 grid, size_t lds, hipStream_t st)
 {
     allow_lds(spread_kernel<T, D, FUSED, CPLX, SNAP>, lds);
-    spread_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(a);
+    spread_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(a, o);
 }
 
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
-static void launch_spread_k(const SpreadTable& m, dim3 grid, size_t lds, hipStream_t st)
+static void launch_spread_k(const SpreadTable& m, const EpilogueOut& o, dim3 grid, size_t lds, hipStream_t st)
 {
     allow_lds(spread_multi_kernel<T, D, FUSED, CPLX, SNAP>, lds);
-    spread_multi_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(m);
+    spread_multi_kernel<T, D, FUSED, CPLX, SNAP><<<grid, dim3(kBlock), lds, st>>>(m, o);
 }
 
 template <typename T, int D, bool CPLX>
-static void launch_runs_k(const SpreadArgs& a, dim3 grid, size_t lds, hipStream_t st)
+static void launch_runs_k(const SpreadArgs& a, const EpilogueOut& o, dim3 grid, size_t lds, hipStream_t st)
 {
     allow_lds(spread_runs_kernel<T, D, CPLX>, lds);
-    spread_runs_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(a);
+    spread_runs_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(a, o);
 }
 
 template <typename T, int D, bool CPLX>
-static void launch_runs_k(const SpreadTable& m, dim3 grid, size_t lds, hipStream_t st)
+static void launch_runs_k(const SpreadTable& m, const EpilogueOut& o, dim3 grid, size_t lds, hipStream_t st)
 {
     allow_lds(spread_runs_multi_kernel<T, D, CPLX>, lds);
-    spread_runs_multi_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(m);
+    spread_runs_multi_kernel<T, D, CPLX><<<grid, dim3(kBlock), lds, st>>>(m, o);
 }
 
 template <typename T, int D, bool SNAP, typename A>
-static void launch_spread_s(const A& a, int fused, int cplx, dim3 grid, size_t lds, hipStream_t st)
+static void launch_spread_s(const A& a, const EpilogueOut& o, int fused, int cplx, dim3 grid, size_t lds,
+                            hipStream_t st)
 {
     if (fused) {
-        if (cplx) launch_spread_k<T, D, true, true, SNAP>(a, grid, lds, st);
-        else launch_spread_k<T, D, true, false, SNAP>(a, grid, lds, st);
+        if (cplx) launch_spread_k<T, D, true, true, SNAP>(a, o, grid, lds, st);
+        else launch_spread_k<T, D, true, false, SNAP>(a, o, grid, lds, st);
     } else {
-        if (cplx) launch_spread_k<T, D, false, true, SNAP>(a, grid, lds, st);
-        else launch_spread_k<T, D, false, false, SNAP>(a, grid, lds, st);
+        if (cplx) launch_spread_k<T, D, false, true, SNAP>(a, o, grid, lds, st);
+        else launch_spread_k<T, D, false, false, SNAP>(a, o, grid, lds, st);
     }
 }
 
@@ -1430,28 +1485,28 @@ template <typename T, int D>
 constexpr bool snap_allowed() { return sizeof(T) == 4 && D <= 12; }
 
 template <typename T, int D, typename A>
-static hipError_t launch_spread_d(const A& a, int fused, int cplx, int snap, int64_t blocks, size_t lds,
-                                  hipStream_t st)
+static hipError_t launch_spread_d(const A& a, const EpilogueOut& o, int fused, int cplx, int snap, int64_t blocks,
+                                  size_t lds, hipStream_t st)
 {
     dim3 grid((unsigned)blocks);
     constexpr bool snap_ok = snap_allowed<T, D>();
     if (fused == 2) {
-        if (cplx) launch_runs_k<T, D, true>(a, grid, lds, st);
-        else launch_runs_k<T, D, false>(a, grid, lds, st);
+        if (cplx) launch_runs_k<T, D, true>(a, o, grid, lds, st);
+        else launch_runs_k<T, D, false>(a, o, grid, lds, st);
     } else if (snap_ok && snap)
-        launch_spread_s<T, D, snap_ok>(a, fused, cplx, grid, lds, st);
+        launch_spread_s<T, D, snap_ok>(a, o, fused, cplx, grid, lds, st);
     else
-        launch_spread_s<T, D, false>(a, fused, cplx, grid, lds, st);
+        launch_spread_s<T, D, false>(a, o, fused, cplx, grid, lds, st);
     return hipGetLastError();
 }
 
 template <typename T, typename A>
-static hipError_t launch_spread_t(const A& a, int deg, int fused, int cplx, int snap, int64_t blocks,
-                                  size_t lds, hipStream_t st)
+static hipError_t launch_spread_t(const A& a, const EpilogueOut& o, int deg, int fused, int cplx, int snap,
+                                  int64_t blocks, size_t lds, hipStream_t st)
 {
     switch (deg) {
 #define NR_CASE(DD) \
-    case DD: return launch_spread_d<T, DD>(a, fused, cplx, snap, blocks, lds, st);
+    case DD: return launch_spread_d<T, DD>(a, o, fused, cplx, snap, blocks, lds, st);
         NR_CASE(2) NR_CASE(3) NR_CASE(4) NR_CASE(5) NR_CASE(6) NR_CASE(7) NR_CASE(8) NR_CASE(9)
         NR_CASE(10) NR_CASE(11) NR_CASE(12) NR_CASE(13) NR_CASE(14) NR_CASE(15) NR_CASE(16)
         NR_CASE(17) NR_CASE(18)
@@ -1460,22 +1515,23 @@ static hipError_t launch_spread_t(const A& a, int deg, int fused, int cplx, int 
     }
 }
 
-hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, hipStream_t st)
+hipError_t launch_spread(const SpreadArgs& a, int fp64, int deg, int fused, const EpilogueOut& out,
+                         hipStream_t st)
 {
     if (a.count <= 0) return hipSuccess;
     const int64_t blocks = spread_blocks(a.count, a.parts);
-    const size_t lds = spread_lds_bytes(fp64, a.n);
-    return fp64 ? launch_spread_t<double>(a, deg, fused, a.strain_complex, a.snap, blocks, lds, st)
-                : launch_spread_t<float>(a, deg, fused, a.strain_complex, a.snap, blocks, lds, st);
+    const size_t lds = spread_lds_bytes(fp64, a.n, a.epi_fused && a.parts == 1);
+    return fp64 ? launch_spread_t<double>(a, out, deg, fused, a.strain_complex, a.snap, blocks, lds, st)
+                : launch_spread_t<float>(a, out, deg, fused, a.strain_complex, a.snap, blocks, lds, st);
 }
 
 hipError_t launch_spread_multi(const SpreadTable& t, int64_t blocks, int fp64, int deg, int fused, int cplx,
-                               int snap, size_t lds, hipStream_t st)
+                               int snap, size_t lds, const EpilogueOut& out, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
     if (t.ncls < 1 || t.ncls > kGroupMax) return hipErrorInvalidValue;
-    return fp64 ? launch_spread_t<double>(t, deg, fused, cplx, snap, blocks, lds, st)
-                : launch_spread_t<float>(t, deg, fused, cplx, snap, blocks, lds, st);
+    return fp64 ? launch_spread_t<double>(t, out, deg, fused, cplx, snap, blocks, lds, st)
+                : launch_spread_t<float>(t, out, deg, fused, cplx, snap, blocks, lds, st);
 }
 
 int64_t epilogue_blocks(const EpilogueArgs& a, int sum_mode)

@@ -108,6 +108,7 @@ struct Class {
     int fp64, w, n, deg, parts;
     int method = NR_METHOD_FUSED;
     int snap = 0;
+    int fuse_epi = 0;                  // the spreader runs the FFT / deconvolution / power itself
     int kmax = 0;                      // largest K of the class
     int64_t grid_off = 0;              // batched mode: the class's grids and point stream
     int64_t pts_off = 0;               //   inside the plan's buffers (bytes)
@@ -141,6 +142,7 @@ static_assert(sizeof(SpreadTable) <= 2048 && sizeof(EpilogueTable) + sizeof(Epil
 struct Group {
     std::vector<int> cls;
     int fp64 = 0, deg = 0, fused = 1, snap = 0;
+    int fuse_epi = 0;                  // epilogue groups: classes whose spreader writes the outputs
     size_t lds[2] = {0, 0};            // spread: [0]; epilogue: [0] spectra, [1] segment sum
     int64_t blocks[2] = {0, 0};
     SpreadTable spread{};              // class tables (kernel arguments)
@@ -233,6 +235,7 @@ void validate(const nr_segment* segs, int32_t n_segs, const nr_template* tmpls, 
         fail(NR_ERR_INVALID_ARG, "parts must be 0, 1, 2, 4, 8 or 16");
     if (o.strain_length < 0 || o.max_workspace_bytes < 0) fail(NR_ERR_INVALID_ARG, "negative size option");
     if (o.moment_mode < 0 || o.moment_mode > 2) fail(NR_ERR_INVALID_ARG, "moment_mode must be 0, 1 or 2");
+    if (o.epilogue < 0 || o.epilogue > 2) fail(NR_ERR_INVALID_ARG, "epilogue must be 0, 1 or 2");
     if (o.flush_period < 0 || o.flush_period > 64 || (o.flush_period & (o.flush_period - 1)))
         fail(NR_ERR_INVALID_ARG, "flush_period must be 0 or a power of two up to 64");
     for (int32_t s = 0; s < n_segs; ++s) {
@@ -420,6 +423,12 @@ constexpr size_t kCellRunMaxSparseLds = kLdsBytes / 5;
 // Longest heterodyne phase span, in phase-table steps, of an instance on the
 // fused spreaders (half the range of their 32-bit table-step conversion).
 constexpr double kFusedMaxPhaseSteps = 1073741824.0;
+
+// LDS occupancy tier: workgroups per compute unit that the LDS allows.
+int lds_tier(size_t bytes)
+{
+    return (int)std::min<size_t>(8, kLdsBytes / std::max<size_t>(bytes, 1));
+}
 
 // Waves per instance when the whole plan has too few waves to fill the chip:
 // enough to bring the samples per lane down to about 64 (at most 16 waves).
@@ -861,6 +870,21 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             k0 = k1;
         }
         P.n_chunks += (int)c.chunks.size();
+        // fused epilogue: the instance's waves share one workgroup (at most
+        // four waves), the FFT's second buffer (one more grid per wave when an
+        // instance has one wave) costs no workgroups per compute unit, and the
+        // plan fills the GPU.  Measured: the 1 h workload (60-cell grids) runs
+        // as fast either way with half the memory traffic, the beta bank (four
+        // waves, 1200 cells) 1 % faster; in the 512-instance ragged batch,
+        // too small to fill the GPU, every workgroup's transform lengthens the
+        // launch it ends (0.32 -> 0.38 ms)
+        {
+            const bool wanted = (o.epilogue == 0 && !small_plan) || o.epilogue == 2;
+            const bool fits = c.method != NR_METHOD_DIRECT && c.parts <= 4 &&
+                              lds_tier(spread_lds_bytes(c.fp64, c.n, c.parts == 1)) >=
+                                  lds_tier(spread_lds_bytes(c.fp64, c.n, 0));
+            c.fuse_epi = wanted && fits ? 1 : 0;
+        }
         // device tables
         c.d_inst.upload(c.inst, "instances");
         c.coef.resize(c.coef.size() + kHornerPad, 0.0);  // whole-width register loads stay in bounds
@@ -1010,6 +1034,14 @@ SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     a.flush_period = c.flush_period;
     a.snap = c.snap;
     a.strain_complex = P.opt.strain_complex;
+    a.epi_fused = c.fuse_epi;
+    a.kmax = c.kmax;
+    a.row_base = c.row_base;
+    a.dec = c.d_dec.p;
+    a.twiddle = c.d_tw.p;
+    a.fft.n = c.n;
+    a.fft.nr = (int32_t)c.radix.size();
+    for (size_t r = 0; r < c.radix.size(); ++r) a.fft.radix[r] = c.radix[r];
     return a;
 }
 
@@ -1038,11 +1070,6 @@ EpilogueArgs epilogue_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     return e;
 }
 
-// LDS occupancy tier: workgroups per compute unit that the LDS allows.
-int lds_tier(size_t bytes)
-{
-    return (int)std::min<size_t>(8, kLdsBytes / std::max<size_t>(bytes, 1));
-}
 
 void build_groups(nr_plan_s& P)
 {
@@ -1050,14 +1077,16 @@ void build_groups(nr_plan_s& P)
     std::map<std::array<int, 5>, size_t> sg;
     // epilogue groups: a segment sum adds into its templates' statistics
     // without atomics, so the classes of one group have disjoint templates
-    std::map<std::array<int, 2>, std::vector<size_t>> eg;
+    std::map<std::array<int, 3>, std::vector<size_t>> eg;
     std::vector<std::vector<char>> eg_tmpls;
     for (size_t ci = 0; ci < P.classes.size(); ++ci) {
         const Class& c = *P.classes[ci];
         if (c.inst.empty()) continue;
         const int fused = spread_code(c.method);
         const int snap = (c.snap && !c.fp64 && c.deg <= 12) ? 1 : 0;
-        const size_t sl = spread_lds_bytes(c.fp64, c.n);
+        // fused and separate-epilogue classes share launches (the flag is per
+        // class in the launch table); their epilogue groups stay apart
+        const size_t sl = spread_lds_bytes(c.fp64, c.n, c.fuse_epi && c.parts == 1);
         const std::array<int, 5> sk{c.fp64, c.deg, fused, snap, lds_tier(sl)};
         auto it = sg.find(sk);
         if (it != sg.end() && P.spread_groups[it->second].cls.size() >= (size_t)kGroupMax) {
@@ -1077,7 +1106,7 @@ void build_groups(nr_plan_s& P)
         g.cls.push_back((int)ci);
         g.lds[0] = std::max(g.lds[0], sl);
         const size_t el = epilogue_lds_bytes(c.fp64, c.n, c.kmax, 1);
-        const std::array<int, 2> ek{c.fp64, lds_tier(el)};
+        const std::array<int, 3> ek{c.fp64, lds_tier(el), c.fuse_epi};
         std::vector<size_t>& cand = eg[ek];
         size_t gi = SIZE_MAX;
         for (size_t q : cand) {
@@ -1094,6 +1123,7 @@ void build_groups(nr_plan_s& P)
             cand.push_back(gi);
             P.epi_groups.emplace_back();
             P.epi_groups.back().fp64 = c.fp64;
+            P.epi_groups.back().fuse_epi = c.fuse_epi;
             eg_tmpls.emplace_back((size_t)P.n_tmpls, (char)0);
         }
         for (int32_t t : c.tmpl_id) eg_tmpls[gi][t] = 1;
@@ -1142,14 +1172,25 @@ void check_finite(nr_plan_s& P, const void* strain)
     if (flag) fail(NR_ERR_NONFINITE_INPUT, "strain contains NaN or Inf");
 }
 
-void run_front(nr_plan_s& P, Class& c, const Chunk& ch)
+// tau (staged classes) and spreading of one chunk; out: the call's outputs
+// for classes whose spreader runs the epilogue (out.mode 0: grids only).
+void run_front(nr_plan_s& P, Class& c, const Chunk& ch, const EpilogueOut& out)
 {
     SpreadArgs a = spread_args(P, c, ch);
     if (c.method == NR_METHOD_STAGED)
         timed_launch(P, NR_STAGE_TAU, [&] { return launch_tau(a, c.fp64, P.stream); }, "tau kernel");
     timed_launch(P, NR_STAGE_SPREAD,
-                 [&] { return launch_spread(a, c.fp64, c.deg, spread_code(c.method), P.stream); },
+                 [&] { return launch_spread(a, c.fp64, c.deg, spread_code(c.method), out, P.stream); },
                  "spread kernel");
+}
+
+// The call's outputs as the spreaders see them (mode: 0 grids, 1 power rows,
+// 2 spectra / power).
+EpilogueOut spread_out(const nr_plan_s& P, EpilogueOut out, int mode)
+{
+    out.mode = mode;
+    out.out_fp64 = P.out_fp64;
+    return out;
 }
 
 // Lane-major strain copies of every class (one launch per destination precision).
@@ -1196,7 +1237,7 @@ hipStream_t lane_stream(const nr_plan_s& P, size_t i, int n)
 
 // Batched mode: per spread group, the tau kernel of its staged classes and
 // then one spread launch; independent groups run on side streams.
-void run_front_batched(nr_plan_s& P)
+void run_front_batched(nr_plan_s& P, const EpilogueOut& out)
 {
     const int ns = side_count(P, P.spread_groups.size());
     fork_side(P, 0, ns);
@@ -1212,13 +1253,13 @@ void run_front_batched(nr_plan_s& P)
         if (g.cls.size() == 1) {
             Class& c = *P.classes[g.cls[0]];
             SpreadArgs a = spread_args(P, c, c.chunks[0]);
-            timed_launch(P, NR_STAGE_SPREAD, [&] { return launch_spread(a, c.fp64, c.deg, g.fused, st); },
+            timed_launch(P, NR_STAGE_SPREAD, [&] { return launch_spread(a, c.fp64, c.deg, g.fused, out, st); },
                          "spread kernel");
             continue;
         }
         timed_launch(P, NR_STAGE_SPREAD, [&] {
             return launch_spread_multi(g.spread, g.blocks[0], g.fp64, g.deg, g.fused, P.opt.strain_complex, g.snap,
-                                       g.lds[0], st);
+                                       g.lds[0], out, st);
         }, "spread kernel");
     }
     join_side(P, 0, ns);
@@ -1229,11 +1270,15 @@ void run_front_batched(nr_plan_s& P)
 // sums of different groups may add into the same templates and stay in order.
 void run_epilogue_batched(nr_plan_s& P, int mode, const EpilogueOut& out)
 {
-    const int ns = mode ? 0 : side_count(P, P.epi_groups.size());
+    // spectra / power rows of fused classes came out of their spreaders
+    std::vector<size_t> todo;
+    for (size_t gi = 0; gi < P.epi_groups.size(); ++gi)
+        if (mode || !P.epi_groups[gi].fuse_epi) todo.push_back(gi);
+    const int ns = mode ? 0 : side_count(P, todo.size());
     fork_side(P, 1, ns);
-    for (size_t gi = 0; gi < P.epi_groups.size(); ++gi) {
-        Group& g = P.epi_groups[gi];
-        hipStream_t st = lane_stream(P, gi, ns);
+    for (size_t ti = 0; ti < todo.size(); ++ti) {
+        Group& g = P.epi_groups[todo[ti]];
+        hipStream_t st = lane_stream(P, ti, ns);
         if (g.cls.size() == 1) {
             Class& c = *P.classes[g.cls[0]];
             EpilogueArgs e = epilogue_args(P, c, c.chunks[0]);
@@ -1307,9 +1352,10 @@ void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* pow
     out.spectra = spectra;
     out.power = power;
     lane_major(P, strain);
+    const EpilogueOut sout = spread_out(P, out, 2);
     if (P.batched) {
         if (spectra || power) {
-            run_front_batched(P);
+            run_front_batched(P, sout);
             run_epilogue_batched(P, 0, out);
         }
     } else {
@@ -1325,8 +1371,9 @@ void execute_launches(nr_plan_s& P, const void* strain, void* spectra, void* pow
                         }, "direct sum");
                     continue;
                 }
-                run_front(P, c, ch);
-                if (spectra || power)
+                if (!(spectra || power)) continue;
+                run_front(P, c, ch, sout);
+                if (!c.fuse_epi)
                     timed_launch(P, NR_STAGE_EPILOGUE,
                                  [&] { return launch_epilogue_spectra(e, out, c.fp64, P.out_fp64, P.stream); },
                                  "epilogue");
@@ -1363,8 +1410,9 @@ void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, vo
         EpilogueOut rows{};
         rows.rows = P.d_rows.p;
         out.rows = P.d_rows.p;
+        const EpilogueOut srows = spread_out(P, rows, 1);
         if (P.batched) {
-            run_front_batched(P);
+            run_front_batched(P, srows);
             run_epilogue_batched(P, 0, rows);
             for (Group& g : P.epi_groups) {
                 if (g.cls.size() == 1) {
@@ -1390,10 +1438,11 @@ void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, vo
                         return launch_direct(a, e, rows, 1, c.fp64, P.out_fp64, P.stream);
                     }, "direct sum");
                 } else {
-                    run_front(P, c, ch);
-                    timed_launch(P, NR_STAGE_EPILOGUE,
-                                 [&] { return launch_epilogue_spectra(e, rows, c.fp64, P.out_fp64, P.stream); },
-                                 "epilogue");
+                    run_front(P, c, ch, srows);
+                    if (!c.fuse_epi)
+                        timed_launch(P, NR_STAGE_EPILOGUE,
+                                     [&] { return launch_epilogue_spectra(e, rows, c.fp64, P.out_fp64, P.stream); },
+                                     "epilogue");
                 }
                 timed_launch(P, NR_STAGE_EPILOGUE, [&] { return launch_rows_sum(e, out, P.out_fp64, P.stream); },
                              "segment sum");
@@ -1401,15 +1450,16 @@ void semicoherent_launches(nr_plan_s& P, const void* strain, const double* w, vo
         }
         return;
     }
+    const EpilogueOut sgrid = spread_out(P, out, 0);
     if (P.batched) {
-        run_front_batched(P);
+        run_front_batched(P, sgrid);
         run_epilogue_batched(P, 1, out);
         return;
     }
     for (auto& cp : P.classes) {
         Class& c = *cp;
         for (const Chunk& ch : c.chunks) {
-            run_front(P, c, ch);
+            run_front(P, c, ch, sgrid);
             EpilogueArgs e = epilogue_args(P, c, ch);
             timed_launch(P, NR_STAGE_EPILOGUE,
                          [&] { return launch_epilogue_sum(e, out, c.fp64, P.out_fp64, P.stream); }, "segment sum");
@@ -1700,6 +1750,7 @@ nr_status nufft_resample_query_class(nr_plan p, int32_t ci, nr_class_info* info)
     info->method = c.method;
     info->flush_period = c.flush_period;
     info->snap = c.snap;
+    info->epi_fused = c.fuse_epi;
     info->n_inst = (int64_t)c.inst.size();
     info->n_points = c.n_points;
     for (const InstDev& d : c.inst) {

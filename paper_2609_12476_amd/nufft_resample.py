@@ -46,7 +46,7 @@ class NrOptions(ctypes.Structure):
                 ("parts", c_int32), ("profile", c_int32), ("use_graph", c_int32),
                 ("strain_length", c_int64), ("max_workspace_bytes", c_int64),
                 ("stream", c_void_p), ("tune_cache", c_char_p), ("tune", c_int32),
-                ("flush_period", c_int32), ("moment_mode", c_int32), ("reserved2", c_int32)]
+                ("flush_period", c_int32), ("moment_mode", c_int32), ("epilogue", c_int32)]
 
 
 class NrPlanInfo(ctypes.Structure):
@@ -68,7 +68,7 @@ class NrClassInfo(ctypes.Structure):
                 ("parts", c_int32), ("n_radix", c_int32), ("radix", c_int32 * 8),
                 ("beta_es", c_double), ("n_inst", c_int64), ("n_points", c_int64),
                 ("method", c_int32), ("flush_period", c_int32), ("snap", c_int32),
-                ("reserved", c_int32), ("series_terms", c_int64), ("fallback_points", c_int64)]
+                ("epi_fused", c_int32), ("series_terms", c_int64), ("fallback_points", c_int64)]
 
 
 # symbol -> (restype, argtypes)
@@ -288,7 +288,7 @@ class Plan:
     def __init__(self, segs, tmpls, inst=None, tol=1e-6, precision="fp32", method="auto",
                  sigma=2.0, strict=False, parts=0, strain_complex=False, strain_length=0,
                  max_workspace_bytes=0, check_finite=False, profile=False, use_graph=False,
-                 tune=False, tune_cache=None, flush_period=0, moment_mode=0, stream=None):
+                 tune=False, tune_cache=None, flush_period=0, moment_mode=0, epilogue="auto", stream=None):
         import torch
         opt = nufft_resample_default_options()
         opt.precision = _PRECISION[precision]
@@ -305,6 +305,7 @@ class Plan:
         opt.tune = int(bool(tune))
         opt.flush_period = int(flush_period)
         opt.moment_mode = int(moment_mode)
+        opt.epilogue = {"auto": 0, "separate": 1, "fused": 2}[epilogue]
         self._tune_cache = tune_cache.encode() if tune_cache else None
         opt.tune_cache = self._tune_cache
         if stream is None and torch.cuda.is_available():

@@ -470,3 +470,60 @@ def test_heterodyne_phase_just_inside_fused_range(gpu, method):
     e = rel(X, Xr)
     say(f"  rel l2 {e:.3e}")
     assert e <= FP32_SPEC
+
+
+# ------------------------------------------------------------ fused epilogue --
+
+@pytest.mark.parametrize("method,parts", [("cellrun", 1), ("cellrun", 2), ("cellrun", 4), ("fused", 1),
+                                          ("fused", 4), ("staged", 2), ("cellrun", 8)])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fused_epilogue_matches_separate_and_oracle(gpu, method, parts, prec):
+    """The spreader's own FFT / deconvolution / power (classes of at most four
+    waves per instance; asked for explicitly, since this plan is too small for
+    the automatic choice) against the separate epilogue kernel and the oracle:
+    spectra, power and segment sums."""
+    say(f"fused epilogue {method} parts={parts} {prec}")
+    w = synth.semicoherent(hours=0.05, n_mc=3, n_sub=3, seed=8)
+    tol = 1e-6 if prec == "fp32" else 1e-10
+    spec, bound = (FP32_SPEC, FP32_SUM) if prec == "fp32" else (FP64_SPEC, FP64_SPEC)
+    kw = dict(precision=prec, tol=tol, method=method, parts=parts)
+    Xf, Pf, vf, off, cf = run_plan(w, gpu, epilogue="fused", **kw)
+    Xs, Ps, vs, _, cs = run_plan(w, gpu, epilogue="separate", **kw)
+    assert [c.epi_fused for c in cf] == [1 if parts <= 4 else 0] * len(cf)
+    assert all(c.epi_fused == 0 for c in cs)
+    assert np.array_equal(vf, vs)
+    ok = vf.astype(bool)
+    Xr, offr, okr = oracle.spectra(w)
+    assert np.array_equal(okr, vf)
+    errs = per_instance_errors(Xf, Xr, off, ok)
+    assert errs.max() <= spec, errs.max()
+    close = 1e-6 if prec == "fp32" else 1e-13
+    assert rel(Xf, Xs) <= close and rel(Pf, Ps) <= close
+    assert np.allclose(Pf, np.abs(Xf) ** 2, rtol=1e-5 if prec == "fp32" else 1e-12, atol=0)
+    Sf, Uf, soff = run_sum(w, gpu, epilogue="fused", **kw)
+    Ss, Us, _ = run_sum(w, gpu, epilogue="separate", **kw)
+    Sr, soffr, Ur = oracle.semicoherent(w)
+    assert np.array_equal(Uf, Us) and np.array_equal(Uf, Ur)
+    for m in range(w.n_tmpl):
+        if Ur[m]:
+            assert rel(Sf[soff[m]:soff[m + 1]], Sr[soffr[m]:soffr[m + 1]]) <= bound
+    assert rel(Sf, Ss) <= close
+
+
+def test_fused_epilogue_in_grouped_launches(gpu):
+    """A ragged batch whose classes of two and four waves per instance run the
+    fused epilogue while the classes of eight and sixteen do not, in shared
+    grouped launches: every spectrum still matches the oracle."""
+    say("fused epilogue in grouped launches")
+    w = synth.ragged_batch(n_inst=30, seed=33)
+    w.inst_tol = np.where(w.inst_tol < 1e-6, 1e-6, w.inst_tol)
+    Xr, off, ok = oracle.spectra(w)
+    X, _, valid, off_g, cls = run_plan(w, gpu, precision="fp32", epilogue="fused")
+    assert np.array_equal(off, off_g) and np.array_equal(valid, ok)
+    fused = {c.epi_fused for c in cls}
+    say(f"  {len(cls)} classes, fused flags {sorted(fused)}")
+    assert fused == {0, 1}
+    for i in range(w.n_inst):
+        if ok[i]:
+            t = float(w.inst_tol[i])
+            assert rel(X[off[i]:off[i + 1]], Xr[off[i]:off[i + 1]]) <= max(t, FP32_SPEC), i

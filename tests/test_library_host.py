@@ -68,7 +68,8 @@ def _opt(**kw):
     ("bad_sigma", nr.NR_ERR_INVALID_ARG), ("bad_parts", nr.NR_ERR_INVALID_ARG),
     ("past_strain", nr.NR_ERR_INVALID_ARG), ("fp32_strict", nr.NR_ERR_TOL_UNATTAINABLE),
     ("fp64_strict", nr.NR_ERR_TOL_UNATTAINABLE), ("huge_grid", nr.NR_ERR_INVALID_ARG),
-    ("bad_precision", nr.NR_ERR_INVALID_ARG), ("huge_phase", nr.NR_ERR_INVALID_ARG)])
+    ("bad_precision", nr.NR_ERR_INVALID_ARG), ("huge_phase", nr.NR_ERR_INVALID_ARG),
+    ("bad_epilogue", nr.NR_ERR_INVALID_ARG)])
 def test_plan_rejects_bad_arguments_before_device_work(case, code):
     segs, tmpls, inst, tol, opt = _segs(), _tmpls(), None, 1e-6, _opt()
     if case == "tol_zero":
@@ -103,6 +104,8 @@ def test_plan_rejects_bad_arguments_before_device_work(case, code):
         opt.precision = 7
     elif case == "huge_phase":
         tmpls[0].f_lo = 1e12          # heterodyne phase beyond FP64 resolution
+    elif case == "bad_epilogue":
+        opt.epilogue = 3
     with pytest.raises(nr.NrError) as e:
         nr.nufft_resample_plan(segs, tmpls, inst, tol, opt)
     assert e.value.code == code
