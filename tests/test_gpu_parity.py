@@ -527,3 +527,69 @@ def test_fused_epilogue_in_grouped_launches(gpu):
         if ok[i]:
             t = float(w.inst_tol[i])
             assert rel(X[off[i]:off[i + 1]], Xr[off[i]:off[i + 1]]) <= max(t, FP32_SPEC), i
+
+
+# ------------------------------------------------------------- error paths --
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_check_finite_reports_nonfinite_strain(gpu, bad):
+    """check_finite scans the strain before any other launch: a NaN or Inf
+    anywhere in a segment gives NR_ERR_NONFINITE_INPUT from execute and from
+    semicoherent_sum, with the outputs untouched; a finite strain runs."""
+    import torch
+    from paper_2609_12476_amd import NR_ERR_NONFINITE_INPUT, NrError, Plan
+    say(f"check_finite {bad}")
+    w = synth.semicoherent(hours=0.02, n_mc=2, n_sub=2, seed=4)
+    with Plan.from_workload(w, precision="fp32", check_finite=True) as p:
+        x = p.strain_tensor(w.strain, gpu)
+        sp, _, valid = p.execute(x)
+        torch.cuda.synchronize()
+        assert bool(valid.bool().any())
+        y = x.clone()
+        y[int(w.seg_len[0]) + 17] = bad                  # inside the second segment
+        sp2 = torch.full_like(sp, 3.0)
+        with pytest.raises(NrError) as e:
+            p.execute(y, sp2)
+        assert e.value.code == NR_ERR_NONFINITE_INPUT
+        stat = torch.full((p.info.stat_bins,), 5.0, dtype=torch.float32, device=gpu)
+        with pytest.raises(NrError) as e:
+            p.semicoherent_sum(y, None, stat)
+        assert e.value.code == NR_ERR_NONFINITE_INPUT
+        torch.cuda.synchronize()
+        assert bool((sp2 == 3.0).all()) and bool((stat == 5.0).all())
+
+
+def test_workspace_cap_chunks_then_refuses(gpu):
+    """A max_workspace_bytes cap below the grids of the whole plan splits every
+    class into chunks (outputs unchanged against the oracle and the uncapped
+    plan); a cap below the plan's fixed tables is NR_ERR_OUT_OF_MEMORY at plan
+    time."""
+    import torch
+    from paper_2609_12476_amd import NR_ERR_OUT_OF_MEMORY, NrError, Plan, complex_view
+    say("workspace cap")
+    w = synth.semicoherent(hours=0.2, n_mc=8, n_sub=20, seed=6)
+    X0, _, v0, off, _ = run_plan(w, gpu, precision="fp32")
+    S0, U0, soff = run_sum(w, gpu, precision="fp32")
+    cap = 3 << 20        # above the two classes' strain copies (1.4 MB) plus one grid chunk, below all grids
+    with Plan.from_workload(w, precision="fp32", max_workspace_bytes=cap) as p:
+        assert p.info.n_chunks > 1 and p.info.workspace_bytes <= 2 * cap
+        x = p.strain_tensor(w.strain, gpu)
+        sp, _, valid = p.execute(x)
+        stat, used = p.semicoherent_sum(x)
+        torch.cuda.synchronize()
+        X = complex_view(sp).cpu().numpy().astype(np.complex128)
+        S = stat.cpu().numpy().astype(np.float64)
+        say(f"  {p.info.n_chunks} chunks, workspace {p.info.workspace_bytes} bytes")
+    assert np.array_equal(valid.cpu().numpy(), v0) and np.array_equal(used.cpu().numpy(), U0)
+    assert rel(X, X0) <= 1e-6
+    for m in range(w.n_tmpl):
+        if U0[m]:
+            assert rel(S[soff[m]:soff[m + 1]], S0[soff[m]:soff[m + 1]]) <= FP32_SUM
+    rng = np.random.default_rng(2)
+    idx = np.sort(rng.choice(np.flatnonzero(v0), size=12, replace=False))
+    Xr, offr, _ = oracle.spectra(w, inst_idx=idx)
+    for j, i in enumerate(idx):
+        assert rel(X[off[i]:off[i + 1]], Xr[offr[j]:offr[j + 1]]) <= FP32_SPEC
+    with pytest.raises(NrError) as e:
+        Plan.from_workload(w, precision="fp32", max_workspace_bytes=64 << 10)
+    assert e.value.code == NR_ERR_OUT_OF_MEMORY
