@@ -2,6 +2,7 @@
 #include "nr_params.hpp"
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <vector>
 
@@ -184,6 +185,46 @@ std::vector<int> fft_radices(int n)
         r.push_back(5);
         n /= 5;
     }
+    return r;
+}
+
+std::vector<std::vector<int>> fft_radix_candidates(int n)
+{
+    const std::vector<int> d = fft_radices(n);
+    std::vector<std::vector<int>> c{d};
+    c.emplace_back(d.rbegin(), d.rend());
+    std::vector<int> s = d;
+    std::sort(s.begin(), s.end(), std::greater<int>());
+    c.push_back(s);
+    std::sort(s.begin(), s.end());
+    c.push_back(s);
+    std::vector<int> twos;
+    for (int q : d) {
+        if (q == 4) {
+            twos.push_back(2);
+            twos.push_back(2);
+        } else {
+            twos.push_back(q);
+        }
+    }
+    c.push_back(twos);
+    std::vector<std::vector<int>> out;
+    for (auto& r : c)
+        if (r.size() <= 8 && std::find(out.begin(), out.end(), r) == out.end()) out.push_back(r);
+    return out;
+}
+
+int radix_code(const std::vector<int>& r)
+{
+    int code = 0;
+    for (int q : r) code = code * 10 + q;
+    return code;
+}
+
+std::vector<int> radix_from_code(int code)
+{
+    std::vector<int> r;
+    for (; code > 0; code /= 10) r.insert(r.begin(), code % 10);
     return r;
 }
 

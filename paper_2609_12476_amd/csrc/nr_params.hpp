@@ -43,4 +43,14 @@ int fft_size(long long m);
 // Radix passes of a 2^a 3^b 5^c size: fours, then a two, threes, fives.
 std::vector<int> fft_radices(int n);
 
+// Orders of radix passes the autotuner times for size n (the default order of
+// fft_radices first, then its reverse, descending and ascending orders and the
+// fours split into twos; duplicates removed).
+std::vector<std::vector<int>> fft_radix_candidates(int n);
+
+// A radix plan as decimal digits, first pass most significant (at most 8
+// passes), and back; code 0 is the empty plan.
+int radix_code(const std::vector<int>& r);
+std::vector<int> radix_from_code(int code);
+
 }  // namespace nr

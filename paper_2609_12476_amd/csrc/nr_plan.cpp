@@ -109,6 +109,7 @@ struct Class {
     int method = NR_METHOD_FUSED;
     int snap = 0;
     int fuse_epi = 0;                  // the spreader runs the FFT / deconvolution / power itself
+    int radix_code = 0;                // FFT radix plan (radix_code digits); 0: fft_radices(n)
     int kmax = 0;                      // largest K of the class
     int64_t grid_off = 0;              // batched mode: the class's grids and point stream
     int64_t pts_off = 0;               //   inside the plan's buffers (bytes)
@@ -154,6 +155,7 @@ struct Group {
 struct nr_plan_s {
     std::string err;
     nr_options opt{};
+    int radix_override = 0;           // autotuner mini-plans: radix_code of every class
     hipStream_t stream = nullptr;
     int32_t n_segs = 0, n_tmpls = 0;
     int64_t n_inst = 0;
@@ -440,25 +442,32 @@ int small_plan_parts(int64_t L)
 }
 
 struct ClassKey {
-    int fp64, w, n, parts, method, flush, snap;
+    int fp64, w, n, parts, method, flush, snap, radix;
     bool operator<(const ClassKey& o) const
     {
-        return std::tie(fp64, w, n, parts, method, flush, snap) <
-               std::tie(o.fp64, o.w, o.n, o.parts, o.method, o.flush, o.snap);
+        return std::tie(fp64, w, n, parts, method, flush, snap, radix) <
+               std::tie(o.fp64, o.w, o.n, o.parts, o.method, o.flush, o.snap, o.radix);
     }
 };
 
 // ------------------------------------------------------------- autotuner --
 
-// Spreader configuration of one shape (precision, kernel width, grid, samples).
+// Spreader configuration and FFT radix plan of one shape (precision, kernel
+// width, grid, samples).
 struct Tuned {
     int method, parts, flush, snap;
     double us_per_inst;
+    int radix;   // radix_code of the fastest FFT plan (0: the default order)
 };
+// batch 0: tuned for throughput on a mini-plan that fills the GPU; > 0: for a
+// plan too small to fill it, on a mini-plan of that many instances.
 struct ShapeKey {
     int fp64, w, n;
-    int64_t L;
-    bool operator<(const ShapeKey& o) const { return std::tie(fp64, w, n, L) < std::tie(o.fp64, o.w, o.n, o.L); }
+    int64_t L, batch;
+    bool operator<(const ShapeKey& o) const
+    {
+        return std::tie(fp64, w, n, L, batch) < std::tie(o.fp64, o.w, o.n, o.L, o.batch);
+    }
 };
 
 std::mutex g_tune_mutex;
@@ -471,11 +480,23 @@ void load_tune_cache(const char* path)
     g_cache_loaded[path] = true;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    ShapeKey k;
-    Tuned t;
-    long long L;
-    while (std::fscanf(f, "%d %d %d %lld %d %d %d %d %lf", &k.fp64, &k.w, &k.n, &L, &t.method, &t.parts,
-                       &t.flush, &t.snap, &t.us_per_inst) == 9) {
+    // one shape per line; the radix plan (tenth field) and the small-plan
+    // batch (eleventh) may be absent
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        ShapeKey k;
+        Tuned t{};
+        long long L, batch = 0;
+        const int got = std::sscanf(line, "%d %d %d %lld %d %d %d %d %lf %d %lld", &k.fp64, &k.w, &k.n, &L,
+                                    &t.method, &t.parts, &t.flush, &t.snap, &t.us_per_inst, &t.radix, &batch);
+        if (got < 9) continue;
+        if (got < 10) t.radix = 0;
+        if (got < 11) batch = 0;
+        k.batch = batch;
+        const std::vector<int> r = radix_from_code(t.radix);
+        int prod = 1;
+        for (int q : r) prod = (q >= 2 && q <= 5 && prod <= k.n) ? prod * q : -1;
+        if (t.radix != 0 && prod != k.n) t.radix = 0;   // not a plan of this size: use the default
         k.L = L;
         g_tuned[k] = t;
     }
@@ -489,9 +510,9 @@ void save_tune_cache(const char* path)
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
     for (auto& kv : g_tuned)
-        std::fprintf(f, "%d %d %d %lld %d %d %d %d %.6f\n", kv.first.fp64, kv.first.w, kv.first.n,
+        std::fprintf(f, "%d %d %d %lld %d %d %d %d %.6f %d %lld\n", kv.first.fp64, kv.first.w, kv.first.n,
                      (long long)kv.first.L, kv.second.method, kv.second.parts, kv.second.flush, kv.second.snap,
-                     kv.second.us_per_inst);
+                     kv.second.us_per_inst, kv.second.radix, (long long)kv.first.batch);
     std::fclose(f);
     std::rename(tmp.c_str(), path);
 }
@@ -521,7 +542,7 @@ void build_class_tables(Class& c, double tol_cls, double sigma)
         tw[2 * t] = cosl(ang);
         tw[2 * t + 1] = sinl(ang);
     }
-    c.radix = fft_radices(c.n);
+    c.radix = c.radix_code ? radix_from_code(c.radix_code) : fft_radices(c.n);
     // coarse heterodyne phasors exp(2 pi i k / N)
     const int NT = phase_table_size(c.fp64);
     std::vector<long double> ph(2 * (size_t)NT);
@@ -545,7 +566,7 @@ void build_class_tables(Class& c, double tol_cls, double sigma)
 }
 
 Tuned tuned_config(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
-                   int w, int n);
+                   int w, int n, int64_t small_batch);
 void build_groups(nr_plan_s& P);
 
 void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_template* tmpls,
@@ -623,9 +644,24 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
     }
     std::vector<double> tmpl_beta(n_tmpls);
     for (int32_t m = 0; m < n_tmpls; ++m) tmpl_beta[m] = chirp_beta(P.tmpls[m].mc_msun, P.tmpls[m].f0);
+    // tuning a plan too small to fill the GPU: how many valid instances each
+    // shape (precision, width, grid, samples) has
+    std::map<std::array<int64_t, 4>, int64_t> shape_count;
+    if (o.tune && small_plan) {
+        for (int64_t i = 0; i < N; ++i) {
+            const nr_segment& g = P.segs[P.inst_seg[i]];
+            const nr_template& t = P.tmpls[P.inst_tmpl[i]];
+            if (!instance_constants(g, t, tmpl_beta[P.inst_tmpl[i]]).valid) continue;
+            const int fp64 = (o.precision == NR_FP64 || (o.precision == NR_AUTO && inst_tol[i] < kFp32MinTol)) ? 1 : 0;
+            const double tol_eff = std::max(inst_tol[i], fp64 ? kFp64MinTol : kFp32MinTol);
+            const int w = kernel_width(tol_eff, sigma);
+            const int n = fft_size(std::max((int64_t)std::ceil(sigma * t.n_bins - 1e-9), (int64_t)2 * w));
+            ++shape_count[{fp64, w, n, g.n_samples}];
+        }
+    }
     // kernel width per distinct tolerance, and the last class looked up
     std::map<std::pair<double, int>, int> width_of;
-    ClassKey last_key{-1, -1, -1, -1, -1, -1, -1};
+    ClassKey last_key{-1, -1, -1, -1, -1, -1, -1, -1};
     std::vector<double> series;
     size_t last_ci = 0;
     for (int64_t i = 0; i < N; ++i) {
@@ -704,12 +740,21 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             parts = cellrun_parts(cellrun_rounds(h, g.n_samples, n, df_i), small_plan, g.n_samples, plan_waves);
         int flush = o.flush_period;
         int snap = o.moment_mode == 2 ? 1 : 0;
+        int radix = P.radix_override;
         if (o.tune) {
-            const Tuned tu = tuned_config(o, g, t, tol_eff, fp64, w, n);
-            parts = tu.parts;
+            const int64_t sb = small_plan ? shape_count[{fp64, w, n, g.n_samples}] : 0;
+            const Tuned tu = tuned_config(o, g, t, tol_eff, fp64, w, n, sb);
             method = tu.method;
             flush = tu.flush;
             snap = tu.snap;
+            radix = tu.radix;
+            if (tu.parts > 0)
+                parts = tu.parts;
+            else if (o.parts == 0)   // automatic waves per instance for the tuned method
+                parts = method == NR_METHOD_CELLRUN
+                            ? cellrun_parts(cellrun_rounds(h, g.n_samples, n, df_i), small_plan, g.n_samples,
+                                            plan_waves)
+                            : small_plan_parts(g.n_samples);
         }
         // the fused spreaders and the direct baseline carry only the series
         // form of tau; instances that need log1p/expm1 get their points from
@@ -720,7 +765,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         // staged path, whose tau kernel reduces the phase modulo one cycle
         if (phase_steps >= kFusedMaxPhaseSteps && method != NR_METHOD_DIRECT) method = NR_METHOD_STAGED;
         if (method == NR_METHOD_CELLRUN) snap = 0;  // moments restart with every run
-        ClassKey key{fp64, w, n, parts, method, flush, snap};
+        ClassKey key{fp64, w, n, parts, method, flush, snap, radix};
         size_t ci;
         const bool same = !(key < last_key) && !(last_key < key);
         auto it = same ? class_of.end() : class_of.find(key);
@@ -739,6 +784,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             c->method = method;
             c->flush_period = flush;
             c->snap = snap;
+            c->radix_code = radix;
             c->beta_es = es_beta(w, sigma);
             P.classes.push_back(std::move(c));
         } else {
@@ -1506,11 +1552,60 @@ double time_config(const nr_options& base, const nr_segment& g, const nr_templat
     return 1e3 * ms / 3.0 / (double)batch;
 }
 
-Tuned tune_shape(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64)
+// Grid size the plan gives this template's instances.
+int fft_size_of_template(const nr_template& t, const nr_segment& g, double sigma_opt, double tol, int fp64)
+{
+    (void)g;
+    const double sigma = sigma_opt > 0.0 ? sigma_opt : 2.0;
+    const int w = kernel_width(std::max(tol, fp64 ? kFp64MinTol : kFp32MinTol), sigma);
+    return fft_size(std::max((int64_t)std::ceil(sigma * t.n_bins - 1e-9), (int64_t)2 * w));
+}
+
+// Epilogue time per instance (microseconds) of one radix plan, with the
+// separate epilogue kernel and the given spreader configuration.
+double time_fft_plan(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
+                     const Tuned& cfg, int radix, const void* strain, void* stat, int32_t* used, int64_t batch)
+{
+    nr_options o2 = base;
+    o2.tune = 0;
+    o2.tune_cache = nullptr;
+    o2.parts = cfg.parts;
+    o2.flush_period = cfg.flush;
+    o2.moment_mode = cfg.snap ? 2 : 1;
+    o2.method = cfg.method;
+    o2.precision = fp64 ? NR_FP64 : NR_FP32;
+    o2.profile = 1;
+    o2.use_graph = 0;
+    o2.check_finite = 0;
+    o2.strain_length = 0;
+    o2.max_workspace_bytes = 0;
+    o2.epilogue = 1;
+    nr_segment s1 = g;
+    s1.sample_offset = 0;
+    std::vector<nr_instance> il((size_t)batch, nr_instance{0, 0, tol});
+    nr_plan_s mini;
+    mini.opt = o2;
+    mini.radix_override = radix;
+    create_plan(mini, &s1, 1, &t, 1, il.data(), batch, tol);
+    semicoherent(mini, strain, nullptr, stat, used);  // warm-up
+    nr_stage_times st{};
+    nufft_resample_stage_times(&mini, &st);
+    for (int r = 0; r < 3; ++r) semicoherent(mini, strain, nullptr, stat, used);
+    nufft_resample_stage_times(&mini, &st);
+    return 1e3 * st.ms[NR_STAGE_EPILOGUE] / 3.0 / (double)batch;
+}
+
+// small_batch > 0: the shape's instances in a plan too small to fill the GPU;
+// the mini-plans then hold that many and keep the automatic waves per
+// instance (which spread small plans over more waves), so that the timings
+// reflect that plan's latency rather than a full GPU's throughput.
+Tuned tune_shape(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
+                 int64_t small_batch)
 {
     const int64_t L = g.n_samples;
     int64_t batch = (int64_t(1) << 25) / std::max<int64_t>(L, 1);
     batch = std::min<int64_t>(4096, std::max<int64_t>(256, batch));
+    if (small_batch > 0) batch = std::min<int64_t>(small_batch, 4096);
     // synthetic N(0,1) strain (values do not change the cost)
     std::mt19937_64 rng(12345);
     std::normal_distribution<double> nd;
@@ -1527,9 +1622,10 @@ Tuned tune_shape(const nr_options& base, const nr_segment& g, const nr_template&
     stat.alloc((size_t)t.n_bins * 8, "tuning output");
     used.alloc(sizeof(int32_t), "tuning output");
     hip_check(hipMemset(stat.p, 0, (size_t)t.n_bins * 8), "tuning output");
-    Tuned best{NR_METHOD_FUSED, default_parts(L), 0, 0, INFINITY};
+    Tuned best{NR_METHOD_FUSED, default_parts(L), 0, 0, INFINITY, 0};
     for (int method : {NR_METHOD_FUSED, NR_METHOD_STAGED, NR_METHOD_CELLRUN})
-        for (int parts : {1, 2, 4}) {
+        for (int parts : {1, 2, 4, 0}) {
+            if ((parts == 0) != (small_batch > 0)) continue;   // 0: automatic, small plans only
             if (parts > 1 && L < (int64_t)kWave * parts * 16) continue;
             for (int flush : {4, 16, 64})
                 for (int snap : {0, 1}) {
@@ -1538,21 +1634,32 @@ Tuned tune_shape(const nr_options& base, const nr_segment& g, const nr_template&
                     if (method == NR_METHOD_CELLRUN && (flush != 16 || snap)) continue;
                     const double us = time_config(base, g, t, tol, fp64, method, parts, flush, snap, strain.p,
                                                   stat.p, (int32_t*)used.p, batch);
-                    if (us < best.us_per_inst) best = Tuned{method, parts, flush, snap, us};
+                    if (us < best.us_per_inst) best = Tuned{method, parts, flush, snap, us, 0};
                 }
         }
+    // FFT radix plan: the epilogue alone, timed for every candidate order
+    const std::vector<std::vector<int>> cand = fft_radix_candidates(fft_size_of_template(t, g, base.sigma, tol, fp64));
+    double best_fft = INFINITY;
+    for (const std::vector<int>& r : cand) {
+        const double us = time_fft_plan(base, g, t, tol, fp64, best, radix_code(r), strain.p, stat.p,
+                                        (int32_t*)used.p, batch);
+        if (us < best_fft) {
+            best_fft = us;
+            best.radix = r == cand[0] ? 0 : radix_code(r);
+        }
+    }
     return best;
 }
 
 Tuned tuned_config(const nr_options& base, const nr_segment& g, const nr_template& t, double tol, int fp64,
-                   int w, int n)
+                   int w, int n, int64_t small_batch)
 {
     std::lock_guard<std::mutex> lock(g_tune_mutex);
     load_tune_cache(base.tune_cache);
-    const ShapeKey key{fp64, w, n, g.n_samples};
+    const ShapeKey key{fp64, w, n, g.n_samples, small_batch};
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) return it->second;
-    const Tuned tu = tune_shape(base, g, t, tol, fp64);
+    const Tuned tu = tune_shape(base, g, t, tol, fp64, small_batch);
     g_tuned[key] = tu;
     save_tune_cache(base.tune_cache);
     return tu;

@@ -411,9 +411,41 @@ def test_autotuned_plan_parity_and_cache(gpu, tmp_path):
             t = w.inst_tol[i]
             bound = max(t, FP32_SPEC) if t >= 1e-6 else max(t, 1e-11)
             assert rel(X[off[i]:off[i + 1]], Xr[off[i]:off[i + 1]]) <= bound
-    # a second plan reads the cache and picks the same configurations
+    # a second plan reads the cache and picks the same configurations and FFT plans
     _, _, _, _, cls2 = run_plan(w, gpu, precision="auto", tune=True, tune_cache=cache)
-    assert [(c.parts, c.method, c.flush_period) for c in cls] == [(c.parts, c.method, c.flush_period) for c in cls2]
+    key = lambda c: (c.parts, c.method, c.flush_period, tuple(c.radix[:c.n_radix]))
+    assert [key(c) for c in cls] == [key(c) for c in cls2]
+    for c in cls:
+        assert int(np.prod(c.radix[:c.n_radix])) == c.n
+
+
+@pytest.mark.parametrize("shape", ["1h", "bank"])
+def test_every_fft_radix_order_the_tuner_tries(gpu, tmp_path, shape):
+    """The autotuner times several orders of the grid's radix passes; every one
+    of them, forced through a tuning-cache entry for the shape (method, waves,
+    flush period, radix plan, and the small-plan batch this plan keys it by),
+    must give the oracle's spectra (n = 60 = 4 3 5 and n = 1200 = 4 4 3 5 5, both ways round,
+    sorted, and with the fours split into twos)."""
+    from paper_2609_12476_amd import Plan
+    say(f"radix orders {shape}")
+    if shape == "1h":
+        w = synth.semicoherent(hours=0.05, n_mc=2, n_sub=2, seed=19).as_float32_strain()
+        n, L = 60, 7680
+        orders = [[4, 3, 5], [5, 3, 4], [5, 4, 3], [3, 4, 5], [2, 2, 3, 5]]
+    else:
+        w = synth.paper_bank(hours=0.05, n_beta=3).as_float32_strain()
+        n, L = 1200, 15360
+        orders = [[4, 4, 3, 5, 5], [5, 5, 3, 4, 4], [5, 5, 4, 4, 3], [3, 4, 4, 5, 5], [2, 2, 2, 2, 3, 5, 5]]
+    Xr, off, ok = oracle.spectra(w)
+    for r in orders:
+        code = int("".join(str(q) for q in r))
+        cache = tmp_path / f"tune_{shape}_{code}.txt"        # the tuner reads each cache path once
+        # small plan: the entry is keyed by the shape's valid instances in it
+        cache.write_text(f"0 8 {n} {L} 3 1 16 0 1.0 {code} {int(ok.sum())}\n")
+        X, _, _, _, cls = run_plan(w, gpu, precision="fp32", tol=1e-6, tune=True, tune_cache=str(cache))
+        assert [list(c.radix[:c.n_radix]) for c in cls] == [r] * len(cls), (r, [list(c.radix[:c.n_radix]) for c in cls])
+        errs = per_instance_errors(X, Xr, off, ok)
+        assert errs.max() <= FP32_SPEC, (r, errs.max())
 
 
 @pytest.mark.parametrize("flush", [1, 8, 64])
