@@ -309,7 +309,7 @@ def stackslide_workload(args, dev):
                 "config": {"workload": "stackslide_1h_120seg_69beta_600bins_2048mc_x8t0", "tracks": n_tracks,
                            "power_reads": reads, "layout": "[beta][bin][segment]"},
                 "layout0_ms": res[0][0],
-                "roofline": {"kernel": "gather_kernel<1>", "bound": "hbm", "achieved": gbs,
+                "roofline": {"kernel": "gather_kernel<1, false>", "bound": "hbm", "achieved": gbs,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
                              "traffic": None, "avg_launch_ms": ms,
                              "note": "the 19.9 MB of spectra stay in the L2/MALL caches across tracks"}})

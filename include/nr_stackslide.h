@@ -70,6 +70,20 @@ nr_status nr_ss_create(nr_ss_plan* out, const nr_ss_geometry* g, const double* b
  * same shape, or NULL) receives each track's segment count. */
 nr_status nr_ss_execute(nr_ss_plan p, const float* power, float* n_sigma, int32_t* n_used);
 
+/* The paper's partial sums for spectra that do not fit the device at once
+ * (Sec. VI: a year of spectra is about 200 GB; the statistic is summed over
+ * ranges of segments kept in memory one at a time): the contribution of the
+ * segments seg_begin .. seg_begin + seg_count - 1 to every track, ADDED to
+ * n_sigma (+=) and n_used (+=, or NULL).  power holds exactly those segments,
+ * in the geometry's layout with seg_count in place of n_seg (segment i at
+ * position i - seg_begin).  Each track's weights are normalised over the whole
+ * track, so summing the ranges of a partition of [0, n_seg) in any order gives
+ * nr_ss_execute's n_sigma up to float rounding and its n_used exactly (start
+ * from zeroed outputs).  NR_ERR_INVALID_ARG unless 0 <= seg_begin and
+ * 1 <= seg_count <= n_seg - seg_begin. */
+nr_status nr_ss_execute_range(nr_ss_plan p, const float* power, int32_t seg_begin, int32_t seg_count,
+                              float* n_sigma, int32_t* n_used);
+
 /* The plan's track tables, copied to the host (synchronous): for chirp mass
  * c, start offset s and lag m (segment i0 + m of a track starting in segment
  * i0): k[(c * t0_steps + s) * n_seg + m], j[...], w2sum[...] (running sum of

@@ -87,11 +87,17 @@ __global__ void tables_kernel(const double* __restrict__ beta_start, const doubl
 // One wave per (chirp mass, start offset, 64 consecutive start segments i0):
 // the lags' table entries are the same for every lane (scalar loads), and in
 // layout 1 the lanes read 64 consecutive segments of one (template, bin).
-template <int LAYOUT>
+// Only the segments of [seg_lo, seg_hi) take part; the power buffer holds
+// exactly those (segment i at position i - seg_lo, n_buf = seg_hi - seg_lo of
+// them).  The weights are normalised over the whole track, so the partial sums
+// of consecutive segment ranges add up to the statistic of the whole track;
+// ACC: out and used are accumulated into (+=), else written.
+template <int LAYOUT, bool ACC>
 __global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict__ P, const SsEntry* __restrict__ tab,
                                                         const int32_t* __restrict__ len, int64_t n_fam, int S,
-                                                        int n_seg, int n_bins, int chunks, double a, double b,
-                                                        float* __restrict__ out, int32_t* __restrict__ used)
+                                                        int n_seg, int n_bins, int chunks, int seg_lo, int seg_hi,
+                                                        double a, double b, float* __restrict__ out,
+                                                        int32_t* __restrict__ used)
 {
     const int64_t wid = uniform64(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
     if (wid >= n_fam * chunks) return;  // whole waves
@@ -101,17 +107,23 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict_
     const int i0 = chunk * kWave + lane;
     const int M = len[cs];
     const SsEntry* __restrict__ row = tab + cs * n_seg;
+    const int n_buf = seg_hi - seg_lo;
     const int lim = n_seg - i0;                       // lags this lane may take
-    const int Mw = min(M, n_seg - chunk * kWave);    // the wave's longest
+    // lags of the wave's lanes that land in [seg_lo, seg_hi)
+    const int m_lo = max(0, seg_lo - (chunk * kWave + kWave - 1));
+    const int m_hi = min(min(M, n_seg - chunk * kWave), seg_hi - chunk * kWave);
     double acc = 0.0;
+    int cnt = 0;
 #pragma unroll 4
-    for (int m = 0; m < Mw; ++m) {
+    for (int m = m_lo; m < m_hi; ++m) {
         const int k = row[m].k, j = row[m].j;
         const double w = row[m].w;
-        if (m < lim) {
-            const int64_t idx = LAYOUT == 0 ? ((int64_t)k * n_seg + i0 + m) * n_bins + j
-                                            : ((int64_t)k * n_bins + j) * n_seg + i0 + m;
+        const int i = i0 + m;
+        if (m < lim && i >= seg_lo && i < seg_hi) {
+            const int64_t idx = LAYOUT == 0 ? ((int64_t)k * n_buf + (i - seg_lo)) * n_bins + j
+                                            : ((int64_t)k * n_bins + j) * n_buf + (i - seg_lo);
             acc += w * (a * (double)P[idx] - b);
+            ++cnt;
         }
     }
     if (i0 < n_seg) {
@@ -119,8 +131,13 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict_
         const double r = Me > 0 ? acc / sqrt(row[Me - 1].w2sum) : 0.0;
         const int c = (int)(cs / S), s = (int)(cs % S);
         const int64_t o = ((int64_t)c * n_seg + i0) * S + s;
-        out[o] = (float)r;
-        if (used) used[o] = Me;
+        if (ACC) {
+            out[o] += (float)r;
+            if (used) used[o] += cnt;
+        } else {
+            out[o] = (float)r;
+            if (used) used[o] = cnt;
+        }
     }
 }
 
@@ -179,6 +196,32 @@ nr_status device_status(nr_ss_plan p, hipError_t e, const char* what)
 }
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+namespace {
+
+nr_status gather(nr_ss_plan p, const float* power, int32_t seg_begin, int32_t seg_count, float* n_sigma,
+                 int32_t* n_used, bool acc)
+{
+    const nr_ss_geometry& g = p->g;
+    const int chunks = (g.n_seg + kWave - 1) / kWave;
+    const int64_t fam = (int64_t)p->n_mc * p->S;
+    const int64_t waves = fam * chunks;
+    const unsigned blocks = (unsigned)((waves * kWave + kBlock - 1) / kBlock);
+    const double a = g.norm / g.sigma, b = g.mu / g.sigma;
+    const int lo = seg_begin, hi = seg_begin + seg_count;
+#define NR_GATHER(LAY, ACC)                                                                                          \
+    gather_kernel<LAY, ACC><<<blocks, kBlock, 0, p->stream>>>(power, p->tab, p->len, fam, p->S, g.n_seg, g.n_bins, \
+                                                              chunks, lo, hi, a, b, n_sigma, n_used)
+    if (g.layout == 0) {
+        if (acc) NR_GATHER(0, true); else NR_GATHER(0, false);
+    } else {
+        if (acc) NR_GATHER(1, true); else NR_GATHER(1, false);
+    }
+#undef NR_GATHER
+    return device_status(p, hipGetLastError(), "stack-slide");
+}
 
 }  // namespace
 
@@ -243,6 +286,7 @@ nr_status nr_ss_create(nr_ss_plan* out, const nr_ss_geometry* g, const double* b
     return NR_OK;
 }
 
+
 nr_status nr_ss_execute(nr_ss_plan p, const float* power, float* n_sigma, int32_t* n_used)
 {
     if (!p) return NR_ERR_INVALID_ARG;
@@ -250,19 +294,22 @@ nr_status nr_ss_execute(nr_ss_plan p, const float* power, float* n_sigma, int32_
         p->err = "power and n_sigma must not be NULL";
         return NR_ERR_INVALID_ARG;
     }
-    const nr_ss_geometry& g = p->g;
-    const int chunks = (g.n_seg + kWave - 1) / kWave;
-    const int64_t fam = (int64_t)p->n_mc * p->S;
-    const int64_t waves = fam * chunks;
-    const unsigned blocks = (unsigned)((waves * kWave + kBlock - 1) / kBlock);
-    const double a = g.norm / g.sigma, b = g.mu / g.sigma;
-    if (g.layout == 0)
-        gather_kernel<0><<<blocks, kBlock, 0, p->stream>>>(power, p->tab, p->len, fam, p->S, g.n_seg, g.n_bins,
-                                                           chunks, a, b, n_sigma, n_used);
-    else
-        gather_kernel<1><<<blocks, kBlock, 0, p->stream>>>(power, p->tab, p->len, fam, p->S, g.n_seg, g.n_bins,
-                                                           chunks, a, b, n_sigma, n_used);
-    return device_status(p, hipGetLastError(), "stack-slide");
+    return gather(p, power, 0, p->g.n_seg, n_sigma, n_used, false);
+}
+
+nr_status nr_ss_execute_range(nr_ss_plan p, const float* power, int32_t seg_begin, int32_t seg_count,
+                              float* n_sigma, int32_t* n_used)
+{
+    if (!p) return NR_ERR_INVALID_ARG;
+    if (!power || !n_sigma) {
+        p->err = "power and n_sigma must not be NULL";
+        return NR_ERR_INVALID_ARG;
+    }
+    if (seg_begin < 0 || seg_count < 1 || seg_begin > p->g.n_seg - seg_count) {
+        p->err = "segment range outside [0, n_seg)";
+        return NR_ERR_INVALID_ARG;
+    }
+    return gather(p, power, seg_begin, seg_count, n_sigma, n_used, true);
 }
 
 nr_status nr_ss_tables(nr_ss_plan p, int32_t* k, int32_t* j, double* w2sum, int32_t* len)

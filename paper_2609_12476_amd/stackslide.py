@@ -23,6 +23,7 @@ SIGNATURES = {
     "nr_ss_create": (c_int32, [ctypes.POINTER(c_void_p), ctypes.POINTER(NrSsGeometry), c_void_p, c_void_p,
                                c_int32, c_int32, c_void_p]),
     "nr_ss_execute": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "nr_ss_execute_range": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_void_p, c_void_p]),
     "nr_ss_tables": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nr_ss_transpose": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "nr_ss_last_error": (c_char_p, [c_void_p]),
@@ -112,6 +113,23 @@ class StackSlide:
         if n_used is None and want_used:
             n_used = torch.empty(shape, dtype=torch.int32, device=power.device)
         _check(lib().nr_ss_execute(self.handle, _ptr(power), _ptr(n_sigma), _ptr(n_used)), self.handle)
+        return n_sigma, n_used
+
+    def execute_range(self, power, seg_begin, seg_count, n_sigma, n_used=None):
+        """Add the contribution of segments [seg_begin, seg_begin + seg_count) to
+        n_sigma (and n_used); power holds just those segments in the plan's layout."""
+        import torch
+        n = self.g.n_beta * seg_count * self.g.n_bins
+        if not (isinstance(power, torch.Tensor) and power.is_cuda and power.dtype == torch.float32
+                and power.is_contiguous() and power.numel() >= n):
+            raise ValueError(f"power must be a contiguous float32 CUDA tensor of {n} values")
+        m = self.n_mc * self.g.n_seg * self.t0_steps
+        if not (n_sigma.is_cuda and n_sigma.dtype == torch.float32 and n_sigma.numel() >= m):
+            raise ValueError("n_sigma must be a float32 CUDA tensor of the plan's track grid")
+        if n_used is not None and not (n_used.is_cuda and n_used.dtype == torch.int32 and n_used.numel() >= m):
+            raise ValueError("n_used must be an int32 CUDA tensor of the plan's track grid")
+        _check(lib().nr_ss_execute_range(self.handle, _ptr(power), int(seg_begin), int(seg_count), _ptr(n_sigma),
+                                         _ptr(n_used)), self.handle)
         return n_sigma, n_used
 
     def tables(self):

@@ -77,6 +77,46 @@ def test_n_sigma_matches_oracle(gpu, layout):
     assert err <= NS_TOL * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_segment_range_partial_sums(gpu, layout):
+    """Sec. VI's partial sums: the statistic accumulated over segment ranges held
+    in memory one at a time (ranges of 7, 1, 10 and 6 segments, summed out of
+    order) equals the whole-array statistic (float rounding of the partials)
+    and the oracle; the segment counts add up exactly."""
+    import torch
+    from paper_2609_12476_amd import stackslide as ss
+    say(f"stack-slide ranges layout {layout}")
+    n_seg, n_bins, L, S = 24, 600, 15360, 2
+    mcs = np.array([5e-4, 1e-2, 4e-2, 9e-2])
+    P = synth.noise_power(len(BETAS), n_seg, n_bins, L, seed=5)
+    ranges = [(7, 1), (17, 7), (0, 7), (8, 9)]      # (start, count): a partition of [0, 24), out of order
+    assert sorted(a for a, _ in ranges) == [0, 7, 8, 17] and sum(c for _, c in ranges) == n_seg
+    with _plan(n_seg, n_bins, mcs, S, L, layout=layout) as p:
+        full = torch.from_numpy(P).to(gpu)
+        if layout == 1:
+            full = ss.nr_ss_transpose(full, len(BETAS), n_seg, n_bins)
+        ns_full, used_full = p.execute(full)
+        ns = torch.zeros_like(ns_full)
+        used = torch.zeros_like(used_full)
+        for a, c in ranges:
+            part = torch.from_numpy(np.ascontiguousarray(P[:, a:a + c, :])).to(gpu)
+            if layout == 1:
+                part = ss.nr_ss_transpose(part, len(BETAS), c, n_bins)
+            p.execute_range(part, a, c, ns, used)
+        torch.cuda.synchronize()
+        ns, used = ns.cpu().numpy(), used.cpu().numpy()
+        ns_full, used_full = ns_full.cpu().numpy(), used_full.cpu().numpy()
+    ref, cnt = oss.n_sigma(P, mcs, S, 30.0, BETAS, 40.0, 1.0 / 30.0, 40.0, 60.0, 2.0 / L)
+    assert np.array_equal(used, used_full) and np.array_equal(used, cnt)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(ns - ns_full).max() <= 4 * NS_TOL * scale
+    assert np.abs(ns - ref).max() <= 4 * NS_TOL * scale
+    from paper_2609_12476_amd import NrError
+    with pytest.raises(NrError):
+        with _plan(n_seg, n_bins, mcs, S, L, layout=layout) as p:
+            p.execute_range(torch.from_numpy(P).to(gpu), 20, 5, torch.zeros(len(mcs), n_seg * S, device=gpu))
+
+
 def test_transpose_is_exact(gpu):
     import torch
     from paper_2609_12476_amd import stackslide as ss
