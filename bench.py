@@ -107,6 +107,23 @@ def algorithmic_ops(classes):
     return tot
 
 
+def spread_fft_bytes(classes, strain_bytes, stat_bins, K):
+    """Algorithmic HBM bytes of the spread, FFT and segment-sum stages of one
+    step: the strain once, the point stream of staged classes (read by the
+    spreader), the grids of classes whose FFT runs in a second kernel (written
+    and read back), the power rows (written, then read by the row sums) and
+    the statistic."""
+    b = strain_bytes + stat_bins * 4
+    for c in classes:
+        csize = 16 if c.fp64 else 8
+        if c.method == 1:                                    # NR_METHOD_STAGED
+            b += c.n_points * csize
+        if not c.epi_fused:
+            b += 2 * c.n_inst * c.n * csize
+        b += 2 * c.n_inst * K * 4
+    return b
+
+
 def time_steps(plan, x, stat, used, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -583,7 +600,8 @@ def main():
     out["roofline"] = roof
     # spread + FFT HBM figure of the metric: algorithmic bytes of the spread and
     # FFT/epilogue kernels over their summed time
-    sf_bytes = (pts * 8 if args.method == "staged" else 0) + 2 * info.n_valid * n * 8 + info.stat_bins * 8
+    sf_bytes = spread_fft_bytes(cls, x32.numel() * x32.element_size(), info.stat_bins, 30)
+    out["spread_fft_hbm_bytes"] = sf_bytes
     out["spread_fft_hbm_gbs"] = sf_bytes / ((stage_ms["spread"] + stage_ms["epilogue"]) * 1e-3) / 1e9
     out["spread_fft_hbm_frac"] = out["spread_fft_hbm_gbs"] / HBM_PEAK_GBS
 

@@ -89,6 +89,9 @@ struct SpreadArgs {
     const void* dec;         // [n] real deconvolution factors indexed by mode mod n
     const void* twiddle;     // [n] complex exp(-2 pi i t / n)
     FftPlanDev fft;
+    // single-class launches: logical workgroup of each hardware workgroup
+    // (NULL: the identity)
+    const int32_t* block_order;
 };
 
 // Workgroups of one launch of a class chunk, and grid slots per instance:

@@ -207,6 +207,13 @@ __device__ __forceinline__ Reduced unpack_point<double>(double2 p)
 
 __device__ __forceinline__ double half_width_periods(int w, int n) { return 0.5 * (double)w / (double)n; }
 
+// Logical workgroup of this hardware workgroup in a single-class spread
+// launch: the plan may hand each XCD a segment-local share of the work.
+__device__ __forceinline__ int64_t logical_block(const SpreadArgs& a)
+{
+    return a.block_order ? (int64_t)a.block_order[blockIdx.x] : (int64_t)blockIdx.x;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void tau_kernel(SpreadArgs a)
 {
@@ -771,7 +778,7 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, const Epilogue
 template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
 __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a, EpilogueOut o)
 {
-    spread_block<T, D, FUSED, CPLX, SNAP>(a, o, blockIdx.x);
+    spread_block<T, D, FUSED, CPLX, SNAP>(a, o, logical_block(a));
 }
 
 // ------------------------------------------------- cell-run schedule --
@@ -949,7 +956,7 @@ template <typename T, int D, bool CPLX>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(RunsWaves<T, D, CPLX>::value))) void
 spread_runs_kernel(SpreadArgs a, EpilogueOut o)
 {
-    spread_runs_block<T, D, CPLX>(a, o, blockIdx.x);
+    spread_runs_block<T, D, CPLX>(a, o, logical_block(a));
 }
 
 // Class of workgroup b of a multi-class launch (block_off is ascending).

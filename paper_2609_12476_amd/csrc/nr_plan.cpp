@@ -102,6 +102,7 @@ struct DevBuf {
 struct Chunk {
     int64_t first, count, pt_base;
     int32_t tmpl_first, tmpl_count;
+    int64_t order_off = -1;            // first entry of its workgroup order in Class::d_order (-1: none)
 };
 
 struct Class {
@@ -130,8 +131,46 @@ struct Class {
     std::vector<int32_t> entry_seg;    // segment of each template-major list entry
     int64_t row_base = 0;              // two-pass sum: first element of the class's power rows
     DevBuf d_inst, d_coef, d_taps, d_dec, d_tw, d_phase, d_strain, d_tmpl_id, d_tmpl_list,
-        d_tmpl_list_off, d_tmpl_stat_off, d_entry_seg;
+        d_tmpl_list_off, d_tmpl_stat_off, d_entry_seg, d_order;
 };
+
+// XCD-aware workgroup order.  The GPU deals the workgroups of a launch to its
+// eight XCDs in turn (workgroup b to XCD b mod 8), and each XCD has its own
+// L2; in list order every XCD would meet every segment and fetch the whole
+// strain.  Large single-class launches instead sort their logical workgroups
+// by segment and give each XCD one contiguous share of that order, so each L2
+// fetches about an eighth of the strain.
+constexpr int kXcds = 8;
+constexpr int64_t kOrderMinBlocks = 2048;
+
+void build_block_order(Class& c)
+{
+    std::vector<int32_t> order;
+    for (Chunk& ch : c.chunks) {
+        ch.order_off = -1;
+        if (c.method == NR_METHOD_DIRECT) continue;
+        const int64_t G = spread_blocks(ch.count, c.parts);
+        if (G < kOrderMinBlocks || G > INT32_MAX) continue;
+        std::vector<std::pair<int32_t, int32_t>> key((size_t)G);   // (segment of the first item, block)
+        bool several = false;
+        for (int64_t b = 0; b < G; ++b) {
+            const int64_t item = c.parts <= 4 ? b * (4 / c.parts) : b / (c.parts / 4);
+            key[b] = {c.inst[ch.first + item].seg, (int32_t)b};
+            several = several || key[b].first != key[0].first;
+        }
+        if (!several) continue;
+        std::sort(key.begin(), key.end());
+        ch.order_off = (int64_t)order.size();
+        order.resize(order.size() + (size_t)G);
+        int32_t* o = order.data() + ch.order_off;
+        const int64_t q = G / kXcds, r = G % kXcds;
+        for (int64_t b = 0; b < G; ++b) {
+            const int64_t x = b % kXcds;       // XCD of hardware workgroup b, and its turn there
+            o[b] = key[x * q + std::min(x, r) + b / kXcds].second;
+        }
+    }
+    if (!order.empty()) c.d_order.upload(order, "workgroup order");
+}
 
 // The class tables of grouped launches travel in the kernel arguments
 // (limited to 4 KiB).
@@ -931,6 +970,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
                                   lds_tier(spread_lds_bytes(c.fp64, c.n, 0));
             c.fuse_epi = wanted && fits ? 1 : 0;
         }
+        build_block_order(c);
         // device tables
         c.d_inst.upload(c.inst, "instances");
         c.coef.resize(c.coef.size() + kHornerPad, 0.0);  // whole-width register loads stay in bounds
@@ -949,7 +989,7 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         P.workspace += (int64_t)(c.d_inst.bytes + c.d_coef.bytes + c.d_strain.bytes +
                                  c.d_phase.bytes + c.d_taps.bytes + c.d_dec.bytes + c.d_tw.bytes + c.d_tmpl_id.bytes +
                                  c.d_tmpl_list.bytes + c.d_tmpl_list_off.bytes + c.d_tmpl_stat_off.bytes +
-                                 c.d_entry_seg.bytes);
+                                 c.d_entry_seg.bytes + c.d_order.bytes);
     }
     if (fixed_bytes + grid_chunk_bytes + point_chunk_bytes > cap)
         fail(NR_ERR_OUT_OF_MEMORY, "workspace of " + std::to_string(fixed_bytes + grid_chunk_bytes + point_chunk_bytes) +
@@ -1088,6 +1128,7 @@ SpreadArgs spread_args(const nr_plan_s& P, const Class& c, const Chunk& ch)
     a.fft.n = c.n;
     a.fft.nr = (int32_t)c.radix.size();
     for (size_t r = 0; r < c.radix.size(); ++r) a.fft.radix[r] = c.radix[r];
+    a.block_order = ch.order_off >= 0 ? (const int32_t*)c.d_order.p + ch.order_off : nullptr;
     return a;
 }
 
@@ -1184,6 +1225,7 @@ void build_groups(nr_plan_s& P)
         for (size_t q = 0; q < g.cls.size(); ++q) {
             const Class& c = *P.classes[g.cls[q]];
             g.spread.a[q] = spread_args(P, c, c.chunks[0]);
+            g.spread.a[q].block_order = nullptr;     // grouped launches keep list order
             g.spread.block_off[q] = off;
             off += spread_blocks(c.chunks[0].count, c.parts);
         }
