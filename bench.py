@@ -328,7 +328,8 @@ def stackslide_workload(args, dev):
                 "layout0_ms": res[0][0],
                 "roofline": {"kernel": "gather_kernel<1, false>", "bound": "hbm", "achieved": gbs,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                             "traffic": None, "avg_launch_ms": ms,
+                             "traffic": committed_traffic("gather_kernel<1, false>"),
+                             "traffic_unit": "bytes per launch", "avg_launch_ms": ms,
                              "note": "the 19.9 MB of spectra stay in the L2/MALL caches across tracks"}})
     # sampled parity and the oracle's rate on the host
     P = power.cpu().numpy().astype(np.float64).reshape(len(betas), n_seg, K)

@@ -13,8 +13,9 @@
  * Precision: FP32 master parameters; the weight matrices and the output
  * vector are multiplied as bfloat16 (rounded to nearest even from the
  * masters after every update) with FP32 activations and FP32 accumulation;
- * weight gradients accumulate in FP64 in a fixed order, so every call is
- * bitwise reproducible.
+ * weight gradients are FP32 matrix-core products over fixed chunks of the
+ * batch whose partial results are added in FP64 in chunk order, so every
+ * call is bitwise reproducible.
  *
  * Parameter vector (NR_MLP_PARAMS = 82,689 floats):
  *   W1[256][64], b1[256], W2[256][256], b2[256], w3[256], b3[1]

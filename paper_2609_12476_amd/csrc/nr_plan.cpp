@@ -958,13 +958,14 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         // fused epilogue: the instance's waves share one workgroup (at most
         // four waves), the FFT's second buffer (one more grid per wave when an
         // instance has one wave) costs no workgroups per compute unit, and the
-        // plan fills the GPU.  Measured: the 1 h workload (60-cell grids) runs
-        // as fast either way with half the memory traffic, the beta bank (four
-        // waves, 1200 cells) 1 % faster; in the 512-instance ragged batch,
-        // too small to fill the GPU, every workgroup's transform lengthens the
-        // launch it ends (0.32 -> 0.38 ms)
+        // plan has at least 4096 waves.  Measured: the 1 h workload (60-cell
+        // grids) runs as fast either way with half the memory traffic, the
+        // beta bank (8280 instances of four waves, 1200 cells) 1 % faster; in
+        // the 512-instance ragged batch, too small to fill the GPU, every
+        // workgroup's transform lengthens the launch it ends (0.32 -> 0.38 ms)
         {
-            const bool wanted = (o.epilogue == 0 && !small_plan) || o.epilogue == 2;
+            const bool wanted =
+                (o.epilogue == 0 && (!small_plan || plan_waves >= kLargePlanWaves)) || o.epilogue == 2;
             const bool fits = c.method != NR_METHOD_DIRECT && c.parts <= 4 &&
                               lds_tier(spread_lds_bytes(c.fp64, c.n, c.parts == 1)) >=
                                   lds_tier(spread_lds_bytes(c.fp64, c.n, 0));

@@ -87,11 +87,12 @@ __global__ void tables_kernel(const double* __restrict__ beta_start, const doubl
 // One wave per (chirp mass, start offset, 64 consecutive start segments i0):
 // the lags' table entries are the same for every lane (scalar loads), and in
 // layout 1 the lanes read 64 consecutive segments of one (template, bin).
-// Only the segments of [seg_lo, seg_hi) take part; the power buffer holds
-// exactly those (segment i at position i - seg_lo, n_buf = seg_hi - seg_lo of
-// them).  The weights are normalised over the whole track, so the partial sums
-// of consecutive segment ranges add up to the statistic of the whole track;
-// ACC: out and used are accumulated into (+=), else written.
+// ACC: only the segments of [seg_lo, seg_hi) take part, the power buffer
+// holds exactly those (segment i at position i - seg_lo, n_buf = seg_hi -
+// seg_lo of them), and out and used are accumulated into (+=).  The weights
+// are normalised over the whole track, so the partial sums of consecutive
+// segment ranges add up to the statistic of the whole track.  Otherwise the
+// buffer holds every segment and out and used are written.
 template <int LAYOUT, bool ACC>
 __global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict__ P, const SsEntry* __restrict__ tab,
                                                         const int32_t* __restrict__ len, int64_t n_fam, int S,
@@ -107,11 +108,13 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict_
     const int i0 = chunk * kWave + lane;
     const int M = len[cs];
     const SsEntry* __restrict__ row = tab + cs * n_seg;
-    const int n_buf = seg_hi - seg_lo;
+    // the whole array (ACC false) needs no range tests: every lag below lim is in it
+    const int lo = ACC ? seg_lo : 0, hi = ACC ? seg_hi : n_seg;
+    const int n_buf = hi - lo;
     const int lim = n_seg - i0;                       // lags this lane may take
-    // lags of the wave's lanes that land in [seg_lo, seg_hi)
-    const int m_lo = max(0, seg_lo - (chunk * kWave + kWave - 1));
-    const int m_hi = min(min(M, n_seg - chunk * kWave), seg_hi - chunk * kWave);
+    // lags of the wave's lanes that land in [lo, hi)
+    const int m_lo = ACC ? max(0, lo - (chunk * kWave + kWave - 1)) : 0;
+    const int m_hi = min(min(M, n_seg - chunk * kWave), hi - chunk * kWave);
     double acc = 0.0;
     int cnt = 0;
 #pragma unroll 4
@@ -119,11 +122,11 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict_
         const int k = row[m].k, j = row[m].j;
         const double w = row[m].w;
         const int i = i0 + m;
-        if (m < lim && i >= seg_lo && i < seg_hi) {
-            const int64_t idx = LAYOUT == 0 ? ((int64_t)k * n_buf + (i - seg_lo)) * n_bins + j
-                                            : ((int64_t)k * n_bins + j) * n_buf + (i - seg_lo);
+        if (m < lim && (!ACC || (i >= lo && i < hi))) {
+            const int64_t idx = LAYOUT == 0 ? ((int64_t)k * n_buf + (i - lo)) * n_bins + j
+                                            : ((int64_t)k * n_bins + j) * n_buf + (i - lo);
             acc += w * (a * (double)P[idx] - b);
-            ++cnt;
+            if (ACC) ++cnt;
         }
     }
     if (i0 < n_seg) {
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict_
             if (used) used[o] += cnt;
         } else {
             out[o] = (float)r;
-            if (used) used[o] = cnt;
+            if (used) used[o] = max(Me, 0);
         }
     }
 }
