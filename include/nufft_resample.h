@@ -166,7 +166,9 @@ typedef struct {
                                    one kernel), unless the FFT's second buffer would cost the
                                    spreader workgroups per compute unit; 1: always a separate
                                    epilogue kernel reading the grids from memory; 0: as 2 in
-                                   plans that fill the GPU (16384 or more waves), else as 1 */
+                                   plans of at least 4096 waves, counted at the default waves
+                                   per instance (one up to 16,384 samples, two up to 32,768,
+                                   four beyond), else as 1 */
 } nr_options;
 
 typedef struct {
