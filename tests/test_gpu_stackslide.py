@@ -55,12 +55,13 @@ def test_tables_match_oracle(gpu):
     assert ln[0].min() == n_seg and ln[-1].max() < n_seg          # tiny Mc never ends, heavy ones do
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-def test_n_sigma_matches_oracle(gpu, layout):
+# S: start offsets per segment (track families per chirp mass)
+@pytest.mark.parametrize("layout,S", [(0, 2), (1, 2), (1, 20)])
+def test_n_sigma_matches_oracle(gpu, layout, S):
     import torch
     from paper_2609_12476_amd import stackslide as ss
-    say(f"stack-slide n_sigma layout {layout}")
-    n_seg, n_bins, L, S = 24, 600, 15360, 2
+    say(f"stack-slide n_sigma layout {layout} S {S}")
+    n_seg, n_bins, L = 24, 600, 15360
     mcs = np.array([5e-4, 1e-2, 4e-2, 9e-2])
     P = synth.noise_power(len(BETAS), n_seg, n_bins, L, seed=3)
     Pd = torch.from_numpy(P).to(gpu)
@@ -77,16 +78,16 @@ def test_n_sigma_matches_oracle(gpu, layout):
     assert err <= NS_TOL * max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-def test_segment_range_partial_sums(gpu, layout):
+@pytest.mark.parametrize("layout,S", [(0, 2), (1, 2), (0, 20)])
+def test_segment_range_partial_sums(gpu, layout, S):
     """Sec. VI's partial sums: the statistic accumulated over segment ranges held
     in memory one at a time (ranges of 7, 1, 10 and 6 segments, summed out of
     order) equals the whole-array statistic (float rounding of the partials)
     and the oracle; the segment counts add up exactly."""
     import torch
     from paper_2609_12476_amd import stackslide as ss
-    say(f"stack-slide ranges layout {layout}")
-    n_seg, n_bins, L, S = 24, 600, 15360, 2
+    say(f"stack-slide ranges layout {layout} S {S}")
+    n_seg, n_bins, L = 24, 600, 15360
     mcs = np.array([5e-4, 1e-2, 4e-2, 9e-2])
     P = synth.noise_power(len(BETAS), n_seg, n_bins, L, seed=5)
     ranges = [(7, 1), (17, 7), (0, 7), (8, 9)]      # (start, count): a partition of [0, 24), out of order
