@@ -249,6 +249,26 @@ def test_small_and_ragged_sizes(gpu, L, K, mc, prec, method):
     assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
 
 
+def test_largest_fp32_grid_and_beyond(gpu):
+    """The largest FP32 grid a spreader workgroup's LDS holds (K = 2430 bins at
+    sigma 2: n = 4860 = 2^2 3^5 5, four per-wave grids and the phase table in
+    160 KB) matches the oracle; the next smooth size (K = 2500, n = 5000) is
+    refused with NR_ERR_INVALID_ARG at plan creation."""
+    from paper_2609_12476_amd import NrError
+    say("largest FP32 grid")
+    w = synth.random_small(77, 6000, 2430, 2e-2, f0=50.0, fs=256.0)
+    Xr, off, ok = oracle.spectra(w)
+    X, _, valid, _, cls = run_plan(w, gpu, precision="fp32", tol=1e-6)
+    say(f"  grid {cls[0].n}, method {cls[0].method}, error {rel(X, Xr):.2e}")
+    assert cls[0].n == 4860
+    assert valid[0] == ok[0] == 1
+    assert rel(X, Xr) <= FP32_SPEC
+    w2 = synth.random_small(78, 6000, 2500, 2e-2, f0=50.0, fs=256.0)
+    with pytest.raises(NrError) as e:
+        run_plan(w2, gpu, precision="fp32", tol=1e-6)
+    assert e.value.code == 1          # NR_ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("K", [28, 30, 31, 32, 33, 34, 40, 48, 60, 62, 63, 64, 66, 72])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_cellrun_round_edges(gpu, K, prec):
