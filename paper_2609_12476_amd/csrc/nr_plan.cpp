@@ -139,7 +139,8 @@ struct Class {
 // L2; in list order every XCD would meet every segment and fetch the whole
 // strain.  Large single-class launches instead sort their logical workgroups
 // by segment and give each XCD one contiguous share of that order, so each L2
-// fetches about an eighth of the strain.
+// meets mostly its own segments (measured on the 1 h workload: strain fetched
+// about 2.8 times instead of 8, since a full GPU does not keep strict turns).
 constexpr int kXcds = 8;
 constexpr int64_t kOrderMinBlocks = 2048;
 
