@@ -71,27 +71,37 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def committed_traffic(kernel_key):
-    """HBM bytes per launch of kernel_key (FETCH_SIZE and WRITE_SIZE scaled by
-    the copy-kernel calibration) from the rocprofv3 summaries under profiles/,
-    or None when none covers it or its kernel sources changed since."""
+def committed_counter(kernel_key, field="traffic_bytes_per_launch"):
+    """A per-launch figure of kernel_key recorded as `field[kernel]: value` in
+    the rocprofv3 summaries under profiles/, or None when none records it or
+    the kernel sources named there changed since it was measured."""
     import glob
     import hashlib
     import re
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         txt = open(path).read()
-        m = re.search(r"traffic_bytes_per_launch\[(.+?)\]: (\d+)", txt)
         h = re.search(r"source_sha256: ([0-9a-f]+)", txt)
         src = re.search(r"sources: (.+)", txt)
-        if not (m and h and src) or m.group(1) != kernel_key:
+        val = None
+        for m in re.finditer(re.escape(field) + r"\[(.+?)\]: (\d+)", txt):
+            if m.group(1) == kernel_key:
+                val = float(m.group(2))
+        if val is None or not (h and src):
             continue
         digest = hashlib.sha256()
         for rel in src.group(1).split():
             with open(os.path.join(ROOT, rel), "rb") as f:
                 digest.update(f.read())
         if digest.hexdigest() == h.group(1):
-            return float(m.group(2))
+            return val
     return None
+
+
+def committed_traffic(kernel_key):
+    """HBM bytes per launch of kernel_key (FETCH_SIZE and WRITE_SIZE scaled by
+    the copy-kernel calibration) from the rocprofv3 summaries under profiles/,
+    or None when none covers it or its kernel sources changed since."""
+    return committed_counter(kernel_key, "traffic_bytes_per_launch")
 
 
 def algorithmic_ops(classes):
@@ -622,6 +632,11 @@ def main():
                 "achieved_basis": "algorithmic VALU lane-operations of the per-sample op model "
                                   "(algorithmic_ops) over the HIP-event launch time; peak = 256 CU x 64 lanes x "
                                   "2.4 GHz, one FP32 or FP64 FMA per lane per cycle"}
+        # executed VALU instructions (SQ_INSTS_VALU of the committed profile)
+        # x 4 cycles each over the SIMD-cycles of the live launch time
+        vi = committed_counter(kname, "valu_instructions_per_launch") if len(cls) == 1 else None
+        if vi is not None:
+            roof["valu_issue_frac_counters"] = vi * 4 / (1024 * 2.4e9 * per_launch_ms * 1e-3)
     else:
         bytes_step = info.n_valid * n * 8 + info.stat_bins * 8
         achieved = bytes_step / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9

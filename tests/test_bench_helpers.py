@@ -54,12 +54,15 @@ def test_committed_traffic_follows_the_sources(tmp_path, monkeypatch):
     digest = hashlib.sha256(src.read_bytes()).hexdigest()
     (tmp_path / "profiles" / "k.md").write_text(
         "# summary\n\ntraffic_bytes_per_launch[nr::k<float>]: 123456\n"
+        "valu_instructions_per_launch[nr::k<float>]: 789\n"
         f"source_sha256: {digest}\nsources: kernel.hip\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.committed_traffic("nr::k<float>") == 123456
+    assert bench.committed_counter("nr::k<float>", "valu_instructions_per_launch") == 789
     assert bench.committed_traffic("nr::other<float>") is None
     src.write_text("kernel v2\n")                    # the kernel changed since the counters were taken
     assert bench.committed_traffic("nr::k<float>") is None
+    assert bench.committed_counter("nr::k<float>", "valu_instructions_per_launch") is None
 
 
 @pytest.mark.parametrize("key", ["nr::spread_runs_kernel<float, 7, false>", "gather_kernel<1, false>"])
