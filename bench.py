@@ -637,6 +637,10 @@ def main():
         vi = committed_counter(kname, "valu_instructions_per_launch") if len(cls) == 1 else None
         if vi is not None:
             roof["valu_issue_frac_counters"] = vi * 4 / (1024 * 2.4e9 * per_launch_ms * 1e-3)
+            roof["valu_issue_basis"] = ("SQ_INSTS_VALU per launch from the committed rocprofv3 summary x 4 cycles "
+                                        "per wave64 instruction / (1024 SIMDs x 2.4 GHz x launch time); about 1 "
+                                        "means the VALU pipeline is saturated (it can exceed 1 slightly where "
+                                        "transcendental instructions issue beside others)")
     else:
         bytes_step = info.n_valid * n * 8 + info.stat_bins * 8
         achieved = bytes_step / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9
