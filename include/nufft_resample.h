@@ -90,11 +90,13 @@ typedef enum {
                              time series to one grid cell (found by binary search on
                              the monotone cell index), so lanes never change cell
                              inside a run and flush together.
-                             The fused methods take instances whose heterodyne phase
-                             spans fewer than 2^30 phase-table steps (1024 per cycle in
-                             FP32, 256 in FP64: about 1e6 and 4e6 cycles of the band
-                             centre over the segment); longer spans, and instances
-                             whose tau needs the log1p/expm1 form, use NR_METHOD_STAGED */
+                             FP64 classes of the fused methods take instances whose
+                             heterodyne phase spans fewer than 2^30 phase-table steps
+                             (256 per cycle: about 4e6 cycles of the band centre over
+                             the segment); longer FP64 spans, and instances whose tau
+                             needs the log1p/expm1 form, use NR_METHOD_STAGED (FP32
+                             classes take the phase's cosine and sine from the
+                             hardware and have no such limit) */
     NR_METHOD_DIRECT = 4  /* baseline: the plain non-uniform DFT on the GPU, every
                              (sample, bin) term, no spreading and no FFT; never
                              chosen automatically; its segment sums need the plan's

@@ -389,13 +389,10 @@ __device__ cpx<T>* fft_team(cpx<T>* buf, const cpx<T>* tw, const FftPlanDev& fp,
 
 // --------------------------------------------------------------- spread --
 
-// exp(2 pi i k / N) for k < N, the coarse part of the heterodyne phasor.
+// exp(2 pi i k / N) for k < N, the coarse part of the FP64 heterodyne phasor
+// (FP32 classes take the phase's cosine and sine from the hardware).
 template <typename T>
 struct PhaseTable;
-template <>
-struct PhaseTable<float> {
-    static constexpr int bits = 10;   // 1024 entries; fine angle |theta| <= pi/1024
-};
 template <>
 struct PhaseTable<double> {
     static constexpr int bits = 8;    // 256 entries; fine angle |theta| <= pi/256
@@ -410,36 +407,61 @@ struct Decoded {
     T u, cr, ci;
 };
 
-// Heterodyned sample value c = x exp(-2 pi i sc / N), N = 2^B table entries:
-// sc = k + theta N / (2 pi), |theta| <= pi / N.  Needs |sc| < 2^31, the
-// range of the 32-bit conversion of k that picks the table entry: the plan
-// gives instances whose phase spans 2^30 table steps or more to the staged
-// method, whose points carry the phase already reduced modulo one cycle.
+// Units of the phase argument of heterodyne_scaled: 2^-kPhaseShift cycles
+// (FP64: table steps; FP32: cycles).
+template <typename T>
+constexpr int phase_shift()
+{
+    if constexpr (sizeof(T) == 4) return 0;
+    else return PhaseTable<T>::bits;
+}
+template <typename T>
+constexpr int kPhaseShift = phase_shift<T>();
+
+// Entries of the phase table a spreader workgroup keeps in LDS.
+template <typename T>
+constexpr int phase_table_entries()
+{
+    if constexpr (sizeof(T) == 4) return 0;
+    else return 1 << PhaseTable<T>::bits;
+}
+
+// Heterodyned sample value c = x exp(-2 pi i phase), sc = phase 2^kPhaseShift.
+// FP32: the phase is reduced to [-1/2, 1/2] cycle in FP64 and its cosine and
+// sine come from the hardware's transcendental unit (arguments in cycles;
+// largest error 1.3e-7 over that range, measured on the device), which works
+// beside the vector ALU.  FP64: N = 2^B table entries, sc = k + theta N /
+// (2 pi), |theta| <= pi / N, the entry times a series in theta; this needs
+// |sc| < 2^31, the range of the 32-bit conversion of k that picks the entry:
+// the plan gives instances whose phase spans 2^30 table steps or more to the
+// staged method, whose points carry the phase already reduced modulo one
+// cycle.
 template <typename T, bool CPLX>
 __device__ __forceinline__ void heterodyne_scaled(double sc, T xr, T xi, const cpx<T>* tab, T& cr, T& ci)
 {
-    constexpr int B = PhaseTable<T>::bits;
-    const double k = rint(sc);
-    const T th = (T)((sc - k) * (6.283185307179586476925 / (double)(1 << B)));
-    const cpx<T> e = tab[(int)k & ((1 << B) - 1)];
-    T cs, sn;
-    const T t2 = th * th;
-    if (sizeof(T) == 4) {
-        cs = fma(t2, T(-0.5), T(1));
-        sn = th;
+    T cs, sn;   // exp(i 2 pi phase) = cs + i sn
+    if constexpr (sizeof(T) == 4) {
+        const float f = (float)(sc - rint(sc));
+        cs = __builtin_amdgcn_cosf(f);
+        sn = __builtin_amdgcn_sinf(f);
     } else {
-        cs = fma(t2, fma(t2, fma(t2, T(-1.0 / 720.0), T(1.0 / 24.0)), T(-0.5)), T(1));
-        sn = fma(th * t2, fma(t2, fma(t2, T(-1.0 / 5040.0), T(1.0 / 120.0)), T(-1.0 / 6.0)), th);
+        constexpr int B = PhaseTable<T>::bits;
+        const double k = rint(sc);
+        const T th = (T)((sc - k) * (6.283185307179586476925 / (double)(1 << B)));
+        const cpx<T> e = tab[(int)k & ((1 << B) - 1)];
+        const T t2 = th * th;
+        const T c = fma(t2, fma(t2, fma(t2, T(-1.0 / 720.0), T(1.0 / 24.0)), T(-0.5)), T(1));
+        const T s = fma(th * t2, fma(t2, fma(t2, T(-1.0 / 5040.0), T(1.0 / 120.0)), T(-1.0 / 6.0)), th);
+        cs = e.x * c - e.y * s;
+        sn = e.y * c + e.x * s;
     }
-    // exp(i 2 pi phase) = e * (cs + i sn); strength = x * conj(that)
-    const T er = e.x * cs - e.y * sn;
-    const T ei = e.y * cs + e.x * sn;
+    // strength = x * conj(exp(i 2 pi phase))
     if (CPLX) {
-        cr = xr * er + xi * ei;
-        ci = xi * er - xr * ei;
+        cr = xr * cs + xi * sn;
+        ci = xi * cs - xr * sn;
     } else {
-        cr = xr * er;
-        ci = -xr * ei;
+        cr = xr * cs;
+        ci = -xr * sn;
     }
 }
 
@@ -447,7 +469,7 @@ __device__ __forceinline__ void heterodyne_scaled(double sc, T xr, T xi, const c
 template <typename T, bool CPLX>
 __device__ __forceinline__ void heterodyne(double phase, T xr, T xi, const cpx<T>* tab, T& cr, T& ci)
 {
-    heterodyne_scaled<T, CPLX>(phase * (double)(1 << PhaseTable<T>::bits), xr, xi, tab, cr, ci);
+    heterodyne_scaled<T, CPLX>(phase * (double)(1 << kPhaseShift<T>), xr, xi, tab, cr, ci);
 }
 
 // Fused path: cell and position straight from dtau.  S = x n with
@@ -659,7 +681,7 @@ template <typename T, int D, bool FUSED, bool CPLX, bool SNAP>
 __device__ __forceinline__ void spread_block(const SpreadArgs& a, const EpilogueOut& o, int64_t lblock)
 {
     using P = typename PointOf<T>::type;
-    constexpr int NT = 1 << PhaseTable<T>::bits;
+    constexpr int NT = phase_table_entries<T>();   // FP32: no table (hardware sine and cosine)
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* lds = tab + NT;
@@ -704,7 +726,7 @@ __device__ __forceinline__ void spread_block(const SpreadArgs& a, const Epilogue
         const int fmask = a.flush_period - 1;
         // fused: grid position in cells and phase in table steps per unit dtau
         const double dfn = tc.df * (double)n, hnn = tc.hn * (double)n;
-        const double fcs = tc.fc * (double)(1 << PhaseTable<T>::bits);
+        const double fcs = tc.fc * (double)(1 << kPhaseShift<T>);
 
         // SNAP: M cumulative, E = snapshot at the end of the parked cell,
         //       S = snapshot at its start.
@@ -855,7 +877,7 @@ __device__ __forceinline__ void cell_quad(const TauConsts& tc, double top, const
 template <typename T, int D, bool CPLX>
 __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, const EpilogueOut& o, int64_t lblock)
 {
-    constexpr int NT = 1 << PhaseTable<T>::bits;
+    constexpr int NT = phase_table_entries<T>();   // FP32: no table (hardware sine and cosine)
     using E = typename std::conditional<CPLX, cpx<T>, T>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* tab = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -892,7 +914,7 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, const Epi
         const int L = d.L;
         // per-sample scales: grid coordinate in cells and phase in table steps
         const double dfn = tc.df * nd, hnn = tc.hn * nd;
-        const double fcs = tc.fc * (double)(1 << PhaseTable<T>::bits);
+        const double fcs = tc.fc * (double)(1 << kPhaseShift<T>);
         const double S1 = grid_coord(dfn, hnn, dtau_of<false>(tc, L > 0 ? L - 1 : 0));
         const double U0 = floor(-hnn), U1 = floor(S1);
         const int rounds = L > 0 ? uniform(((int)(U1 - U0) + kRunsPerRound) / kRunsPerRound) : 0;
@@ -1383,13 +1405,13 @@ static void allow_lds(K* kernel, size_t bytes)
 size_t spread_lds_bytes(int fp64, int n, int pong)
 {
     const size_t csize = fp64 ? 16 : 8;
-    const size_t table = fp64 ? (size_t(1) << PhaseTable<double>::bits) : (size_t(1) << PhaseTable<float>::bits);
+    const size_t table = fp64 ? (size_t)phase_table_entries<double>() : (size_t)phase_table_entries<float>();
     return (table + (size_t)(pong ? 8 : 4) * n) * csize;
 }
 
 int phase_table_size(int fp64)
 {
-    return fp64 ? (1 << PhaseTable<double>::bits) : (1 << PhaseTable<float>::bits);
+    return fp64 ? phase_table_entries<double>() : phase_table_entries<float>();
 }
 
 size_t epilogue_lds_bytes(int fp64, int n, int K_max, int sum_mode)

@@ -462,8 +462,9 @@ constexpr double kCellRunMinDensity = 24.0;
 constexpr double kCellRunMinDensityLarge = 12.0;
 constexpr int64_t kLargePlanWaves = 4096;
 constexpr size_t kCellRunMaxSparseLds = kLdsBytes / 5;
-// Longest heterodyne phase span, in phase-table steps, of an instance on the
-// fused spreaders (half the range of their 32-bit table-step conversion).
+// Longest heterodyne phase span, in phase-table steps, of an FP64 instance on
+// the fused spreaders (half the range of their 32-bit table-step conversion;
+// FP32 classes have no table and no such limit).
 constexpr double kFusedMaxPhaseSteps = 1073741824.0;
 
 // LDS occupancy tier: workgroups per compute unit that the LDS allows.
@@ -749,9 +750,9 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
             // the cycles the segment spans.  An instance whose phase error
             // would exceed a quarter of its tolerance cannot reach it in any
             // precision class: an error in strict plans (otherwise the
-            // phase error bounds what the instance attains).  Counted in phase-table steps (at most 1024
-            // per cycle) the phase must also stay below 2^48, inside the
-            // range of the kernels' rounding to the nearest step.
+            // phase error bounds what the instance attains).  The phase must
+            // also stay below 2^38 cycles, far inside the range of the
+            // kernels' FP64 rounding to the nearest cycle or table step.
             const long double span = h.beta == 0.0 ? h.c * (long double)(g.n_samples - 1)
                                                     : h.a * (1.0L - powl(1.0L - (long double)h.y_max, 0.625L));
             const double fc = t.f_lo + (double)(K / 2) * df_i;
@@ -800,9 +801,10 @@ void create_plan(nr_plan_s& P, const nr_segment* segs, int32_t n_segs, const nr_
         // form of tau; instances that need log1p/expm1 get their points from
         // the tau kernel
         if (ndeg < 0) method = NR_METHOD_STAGED;
-        // the fused spreaders pick the phase-table entry through a 32-bit
+        // the FP64 fused spreaders pick the phase-table entry through a 32-bit
         // conversion of the phase in table steps; longer phase spans take the
         // staged path, whose tau kernel reduces the phase modulo one cycle
+        // (FP32 classes: phase_steps is 0, they have no table)
         if (phase_steps >= kFusedMaxPhaseSteps && method != NR_METHOD_DIRECT) method = NR_METHOD_STAGED;
         if (method == NR_METHOD_CELLRUN) snap = 0;  // moments restart with every run
         ClassKey key{fp64, w, n, parts, method, flush, snap, radix};

@@ -249,23 +249,25 @@ def test_small_and_ragged_sizes(gpu, L, K, mc, prec, method):
     assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
 
 
-def test_largest_fp32_grid_and_beyond(gpu):
-    """The largest FP32 grid a spreader workgroup's LDS holds (K = 2430 bins at
-    sigma 2: n = 4860 = 2^2 3^5 5, four per-wave grids and the phase table in
-    160 KB) matches the oracle; the next smooth size (K = 2500, n = 5000) is
-    refused with NR_ERR_INVALID_ARG at plan creation."""
+@pytest.mark.parametrize("prec,K,n,K_over", [("fp32", 2560, 5120, 2561), ("fp64", 1215, 2430, 1216)])
+def test_largest_grid_and_beyond(gpu, prec, K, n, K_over):
+    """The largest grid a spreader workgroup's LDS holds (four per-wave grids,
+    and in FP64 the 256-entry phase table, in 160 KB: n = 5120 = 2^10 5 in
+    FP32, 2430 = 2 3^5 5 in FP64, at sigma 2) matches the oracle; the next
+    smooth size is refused with NR_ERR_INVALID_ARG at plan creation."""
     from paper_2609_12476_amd import NrError
-    say("largest FP32 grid")
-    w = synth.random_small(77, 6000, 2430, 2e-2, f0=50.0, fs=256.0)
+    say(f"largest grid {prec}")
+    tol = 1e-6 if prec == "fp32" else 1e-10
+    w = synth.random_small(77, 6000, K, 2e-2, f0=50.0, fs=256.0)
     Xr, off, ok = oracle.spectra(w)
-    X, _, valid, _, cls = run_plan(w, gpu, precision="fp32", tol=1e-6)
+    X, _, valid, _, cls = run_plan(w, gpu, precision=prec, tol=tol)
     say(f"  grid {cls[0].n}, method {cls[0].method}, error {rel(X, Xr):.2e}")
-    assert cls[0].n == 4860
+    assert cls[0].n == n
     assert valid[0] == ok[0] == 1
-    assert rel(X, Xr) <= FP32_SPEC
-    w2 = synth.random_small(78, 6000, 2500, 2e-2, f0=50.0, fs=256.0)
+    assert rel(X, Xr) <= (FP32_SPEC if prec == "fp32" else FP64_SPEC)
+    w2 = synth.random_small(78, 6000, K_over, 2e-2, f0=50.0, fs=256.0)
     with pytest.raises(NrError) as e:
-        run_plan(w2, gpu, precision="fp32", tol=1e-6)
+        run_plan(w2, gpu, precision=prec, tol=tol)
     assert e.value.code == 1          # NR_ERR_INVALID_ARG
 
 
@@ -485,22 +487,23 @@ def test_forced_flush_period(gpu, flush):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_heterodyne_phase_beyond_2p31_steps(gpu, method, prec):
     """A band centre of 10 kHz over a 1024 s segment spans about 1e7 cycles of
-    the heterodyne phase: 1e10 phase-table steps in FP32 (1024 per cycle) and
-    2.6e9 in FP64 (256 per cycle), past the 2^31 range of the fused spreaders'
-    table-step conversion.  Whatever method is asked for, the plan must run such
-    an instance on the staged path (phase reduced modulo one cycle) and match the
-    oracle's long-double reduction."""
+    the heterodyne phase: 2.6e9 phase-table steps in FP64 (256 per cycle), past
+    the 2^31 range of the fused spreaders' table-step conversion, so an FP64
+    instance runs on the staged path (phase reduced modulo one cycle) whatever
+    method is asked for.  FP32 classes reduce the phase to half a cycle in FP64
+    and take its cosine and sine from the hardware, with no such range: they
+    keep the method asked for.  Both match the oracle's long-double reduction."""
     say(f"phase beyond 2^31 steps {method} {prec}")
     L, fs = 65536, 64.0
     w = synth.random_small(31, L, 30, 1e-3, f0=50.0, fs=fs, f_lo=10000.0, df=fs / L)
     fc = 10000.0 + 15 * fs / L
-    steps = fc * L / fs * (1024 if prec == "fp32" else 256)
-    assert steps > 2.0 ** 31
+    assert fc * L / fs * 256 > 2.0 ** 31
     Xr, off, ok = oracle.spectra(w)
     assert ok[0]
     X, _, valid, _, cls = run_plan(w, gpu, precision=prec, method=method, tol=1e-6)
     assert valid[0] == 1
-    assert [c.method for c in cls] == [1]          # NR_METHOD_STAGED
+    expect = {"fused": 2, "cellrun": 3, "staged": 1}[method] if prec == "fp32" else 1
+    assert [c.method for c in cls] == [expect]
     e = rel(X, Xr)
     say(f"  rel l2 {e:.3e}")
     assert e <= (FP32_SPEC if prec == "fp32" else 1e-6)
@@ -508,20 +511,20 @@ def test_heterodyne_phase_beyond_2p31_steps(gpu, method, prec):
 
 @pytest.mark.parametrize("method", ["fused", "cellrun"])
 def test_heterodyne_phase_just_inside_fused_range(gpu, method):
-    """Just below 2^30 table steps (about 1e6 cycles in FP32) the fused spreaders
-    keep the instance and match the oracle."""
+    """Just below 2^30 table steps (about 4e6 cycles at 256 per cycle) the FP64
+    fused spreaders keep the instance and match the oracle."""
     say(f"phase inside fused range {method}")
     L, fs = 65536, 64.0
-    f_lo = 900.0                                   # ~9.2e5 cycles over 1024 s: 9.4e8 steps
+    f_lo = 3600.0                                  # ~3.7e6 cycles over 1024 s: 9.4e8 steps
     w = synth.random_small(32, L, 30, 1e-3, f0=50.0, fs=fs, f_lo=f_lo, df=fs / L)
-    steps = (f_lo + 15 * fs / L) * L / fs * 1024
+    steps = (f_lo + 15 * fs / L) * L / fs * 256
     assert 2.0 ** 29 < steps < 2.0 ** 30
     Xr, off, ok = oracle.spectra(w)
-    X, _, valid, _, cls = run_plan(w, gpu, precision="fp32", method=method, tol=1e-6)
+    X, _, valid, _, cls = run_plan(w, gpu, precision="fp64", method=method, tol=1e-6)
     assert [c.method for c in cls] == [2 if method == "fused" else 3]
     e = rel(X, Xr)
     say(f"  rel l2 {e:.3e}")
-    assert e <= FP32_SPEC
+    assert e <= 1e-6
 
 
 # ------------------------------------------------------------ fused epilogue --
