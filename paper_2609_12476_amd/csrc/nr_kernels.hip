@@ -568,6 +568,68 @@ __device__ __forceinline__ void flush(const Moments<T, D>& M, int g, const T* __
     }
 }
 
+// Whole-wave lane shifts (DPP): lane i receives lane i - 1's value; shr
+// gives lane 0 zero, ror gives it lane 63's.
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_ror1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false); }
+template <bool ROT>
+__device__ __forceinline__ float wave_shift(float v)
+{
+    const int b = __float_as_int(v);
+    return __int_as_float(ROT ? dpp_ror1(b) : dpp_shr1(b));
+}
+template <bool ROT>
+__device__ __forceinline__ double wave_shift(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+    const int l2 = ROT ? dpp_ror1(lo) : dpp_shr1(lo);
+    const int h2 = ROT ? dpp_ror1(hi) : dpp_shr1(hi);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)h2 << 32) | (unsigned)l2));
+}
+
+// Flush of one cell-run round.  Lane v holds the moments of the points
+// whose support starts at cell g = U_r + v + 1 (the round's 64 consecutive
+// cells), so tap t of lane v lands on cell g + t, which is also where tap
+// t - 1 of lane v + 1 lands.  The taps are summed across lanes in registers
+// first: folding taps t = w - 1 .. 0 into h = shift(h) + tap_t leaves lane
+// v with the sum of tap_s of lane v - s over s, everything that this round
+// adds to its cell g; the same chain with rotation, fed only by the lanes
+// whose supports pass the round's last cell (v >= 65 - w), leaves lanes
+// v < w - 1 with what lands on cell g + 64.  Each lane then makes one LDS
+// addition per component (two for the lanes carrying that spill) instead of
+// w.  Every lane takes part (empty runs have zero moments), and the order of
+// the additions is fixed, so the result does not depend on scheduling.
+template <typename T, int D>
+__device__ __forceinline__ void flush_round(const Moments<T, D>& M, int g, int lane, const T* __restrict__ A,
+                                            cpx<T>* grid, int n, int w)
+{
+    const bool spill = lane >= kWave + 1 - w;
+    T hr = T(0), hi = T(0), sr = T(0), si = T(0);
+    for (int t = w - 1; t >= 0; --t) {
+        const T* At = A + t * (D + 1);
+        T vr = T(0), vi = T(0);
+#pragma unroll
+        for (int p = 0; p <= D; ++p) {
+            vr = fma(At[p], M.re[p], vr);
+            vi = fma(At[p], M.im[p], vi);
+        }
+        hr = wave_shift<false>(hr) + vr;
+        hi = wave_shift<false>(hi) + vi;
+        sr = wave_shift<true>(sr) + (spill ? vr : T(0));
+        si = wave_shift<true>(si) + (spill ? vi : T(0));
+    }
+    int c = g % n;
+    if (c < 0) c += n;
+    lds_add(&grid[c].x, hr);
+    lds_add(&grid[c].y, hi);
+    if (lane < w - 1) {
+        const int c2 = (c + kWave) % n;
+        lds_add(&grid[c2].x, sr);
+        lds_add(&grid[c2].y, si);
+    }
+}
+
 // Flush the difference of two cumulative moment snapshots.
 template <typename T, int D>
 __device__ __forceinline__ void flush_diff(const Moments<T, D>& E, const Moments<T, D>& P, int g,
@@ -824,20 +886,48 @@ __device__ __forceinline__ double grid_coord(double dfn, double hnn, double dt) 
 // (t - S_0) / m has S_j < t and every j from (t - S_0) / s0 on has S_j >= t.
 // The search runs inside that bracket, widened by two samples against
 // rounding (inv_m = 1 / m, inv_s0 = 1 / s0).
-__device__ __forceinline__ int first_at_least(const TauConsts& tc, int L, double t, double dfn, double hnn,
-                                              double inv_m, double inv_s0)
+// The bisection for a series of degree N fixed at compile time (N < 0: any
+// degree), so that its loop carries no dispatch on the degree; the
+// operations are those of dtau_of.
+template <int N>
+__device__ __forceinline__ int bisect_at_least(const TauConsts& tc, int lo, int hi, double t, double dfn, double hnn)
 {
-    const double d = t + hnn;                     // t - S_0, S_0 = -hnn
-    int lo = (int)fmin(fmax(ceil(d * inv_m) - 2.0, 0.0), (double)L);
-    int hi = (int)fmin(fmax(ceil(d * inv_s0) + 2.0, 0.0), (double)L);
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (grid_coord(dfn, hnn, dtau_of<false>(tc, mid)) < t)
+        const double jd = (double)mid;
+        double dt;
+        if constexpr (N < 0) {
+            dt = dtau_of<false>(tc, mid);
+        } else if constexpr (N == 0) {
+            dt = jd * tc.c;
+        } else {
+            double acc = tc.bc[N - 1];
+#pragma unroll
+            for (int k = N - 2; k >= 0; --k) acc = fma(acc, jd, tc.bc[k]);
+            dt = acc * jd;
+        }
+        if (grid_coord(dfn, hnn, dt) < t)
             lo = mid + 1;
         else
             hi = mid;
     }
     return lo;
+}
+
+__device__ __forceinline__ int first_at_least(const TauConsts& tc, int L, double t, double dfn, double hnn,
+                                              double inv_m, double inv_s0)
+{
+    const double d = t + hnn;                     // t - S_0, S_0 = -hnn
+    const int lo = (int)fmin(fmax(ceil(d * inv_m) - 2.0, 0.0), (double)L);
+    const int hi = (int)fmin(fmax(ceil(d * inv_s0) + 2.0, 0.0), (double)L);
+    switch (tc.ndeg) {
+#define NR_B(N) \
+    case N: return bisect_at_least<N>(tc, lo, hi, t, dfn, hnn);
+        NR_B(0) NR_B(1) NR_B(2) NR_B(3) NR_B(4) NR_B(5) NR_B(6) NR_B(7) NR_B(8) NR_B(9) NR_B(10) NR_B(11)
+        NR_B(12) NR_B(13) NR_B(14) NR_B(15) NR_B(16)
+#undef NR_B
+    default: return bisect_at_least<-1>(tc, lo, hi, t, dfn, hnn);
+    }
 }
 
 template <typename E>
@@ -959,7 +1049,7 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, const Epi
                 if (q < je) cell_quad<T, D, CPLX, true>(tc, top, xs, q, jq, js, je, dfn, hnn, u1, fcs, tab, M);
             }
             // the support of the points of cell U starts at cell U + 1
-            if (je > js) flush<T, D>(M, (int)U + 1, A, grid, n, w);
+            flush_round<T, D>(M, (int)U + 1, lane, A, grid, n, w);
         }
     }
     __syncthreads();
