@@ -80,8 +80,8 @@ def committed_counter(kernel_key, field="traffic_bytes_per_launch"):
     import re
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         txt = open(path).read()
-        h = re.search(r"source_sha256: ([0-9a-f]+)", txt)
-        src = re.search(r"sources: (.+)", txt)
+        h = re.search(r"^source_sha256: ([0-9a-f]+)", txt, re.M)
+        src = re.search(r"^sources: (.+)", txt, re.M)
         val = None
         for m in re.finditer(re.escape(field) + r"\[(.+?)\]: (\d+)", txt):
             if m.group(1) == kernel_key:
@@ -228,6 +228,13 @@ def measure_workload(args, dev, workload, steps, check=16, tune=False, method="a
             ops = algorithmic_ops(cls)
             out["spread_ms_per_step"] = spread_ms
             out["spread_valu_frac"] = ops / (spread_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS
+            # executed VALU instructions of the one spread launch per step, as
+            # recorded per workload in the committed rocprofv3 summary
+            if len(cls) == 1 and cls[0].method == 3 and not cls[0].fp64:
+                key = f"{workload}:nr::spread_runs_kernel<float, {cls[0].degree}, false>"
+                vi = committed_counter(key, "valu_instructions_per_launch")
+                if vi is not None:
+                    out["spread_valu_issue_frac_counters"] = vi * 4 / (1024 * 2.4e9 * spread_ms * 1e-3)
             out["spread_valu_basis"] = "per-sample op model (algorithmic_ops) over the summed spread launches"
         out["stage_ms_per_step"] = {k: v[0] / steps for k, v in stt.items()}
         prof.close()
@@ -733,7 +740,8 @@ def main():
             tuned = name == "ragged_512"
             r = measure_workload(args, dev, name, max(5, args.steps), check=4, tune=tuned)
             out[name] = {k: r[k] for k in ("value", "ms_per_step", "samples_per_s", "spread_ms_per_step",
-                                           "spread_valu_frac", "oracle_check") if k in r}
+                                           "spread_valu_frac", "spread_valu_issue_frac_counters",
+                                           "oracle_check") if k in r}
             out[name]["workload"] = r["config"]["workload"]
             out[name]["unit"] = "spectra/s"
             out[name]["instances"] = r["config"]["instances"]

@@ -65,6 +65,21 @@ def test_committed_traffic_follows_the_sources(tmp_path, monkeypatch):
     assert bench.committed_counter("nr::k<float>", "valu_instructions_per_launch") is None
 
 
+def test_committed_records_ignore_prose(tmp_path, monkeypatch):
+    """Only lines that start with the record names count: prose that happens
+    to contain "sources:" does not hide the record."""
+    (tmp_path / "profiles").mkdir()
+    src = tmp_path / "kernel.hip"
+    src.write_text("kernel\n")
+    digest = hashlib.sha256(src.read_bytes()).hexdigest()
+    (tmp_path / "profiles" / "k.md").write_text(
+        "# summary\n\nmeasured on the earlier sources: other.hip, not these\n\n"
+        "valu_instructions_per_launch[w:nr::k<float>]: 42\n"
+        f"source_sha256: {digest}\nsources: kernel.hip\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.committed_counter("w:nr::k<float>", "valu_instructions_per_launch") == 42
+
+
 @pytest.mark.parametrize("key", ["nr::spread_runs_kernel<float, 7, false>", "gather_kernel<1, false>"])
 def test_committed_profiles_name_their_sources(key):
     """Every committed traffic record names sources that exist, so the check
