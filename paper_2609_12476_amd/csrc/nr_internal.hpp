@@ -16,8 +16,9 @@ constexpr int kMaxRadix = 8;     // FFT passes
 constexpr int kMaxDeg = 18;      // highest Chebyshev degree of the per-cell kernel polynomials
 constexpr int kMaxHorner = 28;   // highest degree of the tau series before the log1p/expm1 form
 
-// Cell-run spreader: a wave deals one run (cell) per lane and round.
-constexpr int kRunsPerRound = kWave;
+// Cell-run spreader: a wave deals one run (cell) per lane and round to all
+// lanes but the last, whose search of the next run's start ends the others.
+constexpr int kRunsPerRound = kWave - 1;
 
 // Per valid instance of a kernel class.  Lane-major point order: the
 // instance's L samples are cut into V = 64 * parts contiguous runs of C

@@ -572,6 +572,8 @@ __device__ __forceinline__ void flush(const Moments<T, D>& M, int g, const T* __
 // gives lane 0 zero, ror gives it lane 63's.
 __device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
 __device__ __forceinline__ int dpp_ror1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false); }
+// lane i receives lane i + 1's value (lane 63 receives zero)
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
 template <bool ROT>
 __device__ __forceinline__ float wave_shift(float v)
 {
@@ -589,9 +591,9 @@ __device__ __forceinline__ double wave_shift(double v)
 }
 
 // Flush of one cell-run round.  Lane v holds the moments of the points
-// whose support starts at cell g = U_r + v + 1 (the round's 64 consecutive
-// cells), so tap t of lane v lands on cell g + t, which is also where tap
-// t - 1 of lane v + 1 lands.  The taps are summed across lanes in registers
+// whose support starts at cell g = U_r + v + 1 (consecutive cells over the
+// wave's lanes; a lane without a cell holds zero moments), so tap t of lane
+// v lands on cell g + t, which is also where tap t - 1 of lane v + 1 lands.  The taps are summed across lanes in registers
 // first: folding taps t = w - 1 .. 0 into h = shift(h) + tap_t leaves lane
 // v with the sum of tap_s of lane v - s over s, everything that this round
 // adds to its cell g; the same chain with rotation, fed only by the lanes
@@ -870,10 +872,11 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(SpreadArgs a, EpilogueOu
 // S_j = n (df dtau_j) - w/2 is sample j's grid coordinate in cells, not
 // reduced modulo the grid; it grows with j, so the unwrapped cell index
 // U_j = floor(S_j) never decreases and the samples sharing one value of U
-// form a contiguous run.  A wave takes 64 consecutive cells per round: lane
-// v finds the first sample past the run of cell U_0 + 64 r + v by a
-// bracketed binary search, the lane before it starts there, every
-// lane accumulates its run's moments without a cell change (its Chebyshev
+// form a contiguous run.  A wave takes 63 consecutive cells per round: lane
+// v finds the first sample of the run of cell U_0 + 63 r + v by a bracketed
+// binary search, the lane before it ends there (lane 63's search only ends
+// lane 62's run), every lane accumulates its run's moments without a cell
+// change (its Chebyshev
 // variable is 1 - 2 (S_j - U), from the same S_j that placed the sample in
 // the run), and all lanes flush together.  The strain is read as aligned
 // quads of samples from a plain per-segment copy.
@@ -1015,25 +1018,17 @@ __device__ __forceinline__ void spread_runs_block(const SpreadArgs& a, const Epi
         // leading series coefficient, kept in a vector register
         double top = tc.ndeg > 0 ? tc.b[tc.ndeg - 1] : 0.0;
         asm volatile("" : "+v"(top));
-        // end of the previous round's last run (a wave that takes every round
-        // starts each round where the last one ended)
-        int carry = 0;
         for (int r = part; r < rounds; r += parts) {
-            // lane v: cell U = U0 + 64 r + v; it searches the end of its run
-            // (the first sample of cell U + 1) and takes the start from the
-            // lane before it
+            // lane v < 63: cell U = U0 + 63 r + v; every lane searches the
+            // start of its cell's run (the first sample at or past cell U),
+            // lanes v < 63 take the end from lane v + 1, and lane 63 takes
+            // no cell (its search gives lane 62's end), so one search per
+            // lane and round serves both ends
             const double U = U0 + (double)(kRunsPerRound * r + lane);
-            const int je = first_at_least(tc, L, U + 1.0, dfn, hnn, inv_m, inv_s0);
-            int js = __shfl_up(je, 1);
-            if (lane == 0) {
-                if (r == 0)
-                    js = 0;     // S_0 >= U0 = floor(S_0)
-                else if (parts == 1)
-                    js = carry;
-                else
-                    js = first_at_least(tc, L, U, dfn, hnn, inv_m, inv_s0);
-            }
-            carry = __builtin_amdgcn_readlane(je, kWave - 1);
+            const int js = (r == 0 && lane == 0) ? 0       // S_0 >= U0 = floor(S_0)
+                                                 : first_at_least(tc, L, U, dfn, hnn, inv_m, inv_s0);
+            int je = dpp_shl1(js);
+            if (lane == kWave - 1) je = js;
             const double u1 = fma(2.0, U, 1.0);
             Moments<T, D> M;
             M.zero();

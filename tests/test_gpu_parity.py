@@ -275,8 +275,8 @@ def test_largest_grid_and_beyond(gpu, prec, K, n, K_over):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_cellrun_round_edges(gpu, K, prec):
     """Cell-run instances whose visited cells fall on both sides of one and
-    two full rounds of 64 cells (one run per lane), so that a round's first
-    run starts where the previous round's last one ended."""
+    two full rounds of 63 cells (one run per lane but the last), so that a
+    round's first run starts where the previous round's last one ended."""
     say(f"cellrun round edges K={K} {prec}")
     w = synth.random_small(100 + K, 2048, K, 3e-2, f0=50.0, fs=64.0, t_start=300.0)
     Xr, off, ok = oracle.spectra(w)
